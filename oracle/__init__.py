@@ -1,0 +1,315 @@
+"""FP64 CPU oracle for speed-limited PIC (SLPIC) -- TEST INFRASTRUCTURE ONLY.
+
+This package is the plain reference that the HIP path is checked against.
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it; the product package never does.  It shares no
+code with the HIP library: the C source ``slpic_oracle.c`` is compiled on its
+own with gcc (``-O2 -ffp-contract=off``) and loaded here with ctypes.
+
+Paper: Werner, Jenkins, Chap & Cary, arXiv:1511.08225 -- Eq. (10), (11a,b),
+Appendix Eq. (A1), (A2).  See ``slpic_oracle.c`` for the readings taken where
+the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slpic_oracle.c")
+_LIB = os.path.join(_HERE, "libslpic_oracle.so")
+
+BETA_STEP, BETA_SMOOTH = 0, 1
+KICK_EXACT, KICK_MMP = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Species(ctypes.Structure):
+    _fields_ = [("charge", ctypes.c_double), ("mass", ctypes.c_double),
+                ("temperature", ctypes.c_double), ("ppc", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("beta_kind", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("u", ctypes.c_double),
+                ("nspecies", ctypes.c_int32), ("source_cells", ctypes.c_int32),
+                ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run", ctypes.c_int32),
+                ("sort_every", ctypes.c_int32), ("sort_bucket", ctypes.c_int32),
+                ("kick", ctypes.c_int32), ("mmp_tol", ctypes.c_double),
+                ("capacity_factor", ctypes.c_double)]
+
+
+_lib = None
+
+_D = ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PU32 = ctypes.POINTER(ctypes.c_uint32)
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_VP = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        sig = {
+            "orc_philox4x32_10": (None, [_PU32, _PU32, _PU32]),
+            "orc_u53": (_D, [ctypes.c_uint32, ctypes.c_uint32]),
+            "orc_beta": (_D, [_I32, _D, _D]),
+            "orc_G": (_D, [_D, _D]),
+            "orc_fast_advance": (_D, [_D, _D, _D]),
+            "orc_kick_exact": (None, [_I32, _D, _D, _PD, _PD, _PD]),
+            "orc_kick_mmp": (_I32, [_I32, _D, _D, _PD, _PD, _D, _I32, _PD]),
+            "orc_Z": (_D, [_I32, _D]),
+            "orc_weight": (_D, [ctypes.POINTER(_Config), _I32]),
+            "orc_load_particle": (None, [ctypes.POINTER(_Config), _I32, ctypes.c_uint32, _PD]),
+            "orc_inject_particle": (None, [ctypes.POINTER(_Config), _I32, ctypes.c_uint32,
+                                           ctypes.c_uint32, _PD]),
+            "orc_poisson1d": (None, [_I32, _D, _PD, _PD, _PD]),
+            "orc_create": (_VP, [ctypes.POINTER(_Config)]),
+            "orc_destroy": (None, [_VP]),
+            "orc_load": (None, [_VP]),
+            "orc_refresh_fields": (None, [_VP]),
+            "orc_step": (None, [_VP, _I32]),
+            "orc_sort": (None, [_VP, _PI32, _PI32]),
+            "orc_keys": (None, [_VP, _I32, _PI32]),
+            "orc_moments": (None, [_VP, _PD]),
+            "orc_nslots": (_I64, [_VP, _I32]),
+            "orc_capacity": (_I64, [_VP, _I32]),
+            "orc_nlive": (_I64, [_VP, _I32]),
+            "orc_step_index": (_I64, [_VP]),
+            "orc_acc_e": (_D, [_VP]),
+            "orc_absorbed_total": (_I64, [_VP, _I32]),
+            "orc_injected_total": (_I64, [_VP, _I32]),
+            "orc_get_particles": (None, [_VP, _I32, _PD, _PD, _PD, _PD]),
+            "orc_set_particles": (_I32, [_VP, _I32, _I64, _PD, _PD, _PD, _PD]),
+            "orc_set_counters": (None, [_VP, _I64, _D]),
+            "orc_get_grid": (None, [_VP, _PD, _PD, _PD, _PD]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_PD)
+
+
+def _beta_kind(v) -> int:
+    if isinstance(v, str):
+        return {"step": BETA_STEP, "smooth": BETA_SMOOTH}[v]
+    return int(v)
+
+
+def make_config(cfg: dict) -> _Config:
+    """Translate a workload dict (see workloads.py) into the oracle's struct."""
+    c = _Config()
+    c.nx = int(cfg["nx"])
+    c.beta_kind = _beta_kind(cfg.get("beta_kind", "step"))
+    c.dx = float(cfg["dx"])
+    c.dt = float(cfg["dt"])
+    c.u = float(cfg["u"])
+    sp = cfg["species"]
+    c.nspecies = len(sp)
+    for k, s in enumerate(sp):
+        c.species[k].charge = float(s["charge"])
+        c.species[k].mass = float(s["mass"])
+        c.species[k].temperature = float(s["temperature"])
+        c.species[k].ppc = int(s["ppc"])
+    c.source_cells = int(cfg.get("source_cells", 4))
+    c.seed = int(cfg.get("seed", 0))
+    c.run = int(cfg.get("run", 0))
+    c.sort_every = int(cfg.get("sort_every", 1))
+    c.sort_bucket = int(cfg.get("sort_bucket", 1))
+    c.kick = {"exact": KICK_EXACT, "mmp": KICK_MMP}[cfg.get("kick", "exact")]
+    c.mmp_tol = float(cfg.get("mmp_tol", 0.01))
+    c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
+    return c
+
+
+# ---------------------------------------------------------------- primitives
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xffffffff for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xffffffff for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def u53(a: int, b: int) -> float:
+    return lib().orc_u53(a & 0xffffffff, b & 0xffffffff)
+
+
+def beta(kind, u: float, speed: float) -> float:
+    return lib().orc_beta(_beta_kind(kind), u, speed)
+
+
+def G(c2: float, p: float) -> float:
+    return lib().orc_G(c2, p)
+
+
+def fast_advance(c2: float, p0: float, K: float) -> float:
+    return lib().orc_fast_advance(c2, p0, K)
+
+
+def kick_exact(kind, u: float, dt: float, v, a) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_kick_exact(_beta_kind(kind), u, dt, _dp(v), _dp(a), _dp(out))
+    return out
+
+
+def kick_mmp(kind, u: float, dt: float, v, a, tol: float, nmax: int = 1 << 20):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.zeros(3)
+    n = lib().orc_kick_mmp(_beta_kind(kind), u, dt, _dp(v), _dp(a), tol, nmax, _dp(out))
+    return out, n
+
+
+def Z(kind, u_over_vt: float) -> float:
+    return lib().orc_Z(_beta_kind(kind), u_over_vt)
+
+
+def weight(cfg: dict, s: int) -> float:
+    c = make_config(cfg)
+    return lib().orc_weight(ctypes.byref(c), s)
+
+
+def load_particle(cfg: dict, s: int, i: int) -> np.ndarray:
+    c = make_config(cfg)
+    out = np.zeros(4)
+    lib().orc_load_particle(ctypes.byref(c), s, i, _dp(out))
+    return out
+
+
+def inject_particle(cfg: dict, s: int, k: int, step: int) -> np.ndarray:
+    c = make_config(cfg)
+    out = np.zeros(4)
+    lib().orc_inject_particle(ctypes.byref(c), s, k, step, _dp(out))
+    return out
+
+
+def poisson1d(nx: int, dx: float, Q: np.ndarray):
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    assert Q.shape == (nx + 1,)
+    phi = np.zeros(nx + 1)
+    E = np.zeros(nx + 1)
+    lib().orc_poisson1d(nx, dx, _dp(Q), _dp(phi), _dp(E))
+    return phi, E
+
+
+# ----------------------------------------------------------------------- run
+class Run:
+    """One 1D3V SLPIC run on the CPU (FP64)."""
+
+    def __init__(self, cfg: dict, load: bool = True):
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        self._h = lib().orc_create(ctypes.byref(self._c))
+        self.nx = self._c.nx
+        self.nspecies = self._c.nspecies
+        if load:
+            lib().orc_load(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    # state ------------------------------------------------------------
+    def step(self, n: int = 1):
+        lib().orc_step(self._h, n)
+
+    def refresh_fields(self):
+        lib().orc_refresh_fields(self._h)
+
+    def sort(self):
+        perms = [np.zeros(max(1, self.nslots(s)), dtype=np.int32) for s in range(2)]
+        n_before = [self.nslots(s) for s in range(2)]
+        lib().orc_sort(self._h, perms[0].ctypes.data_as(_PI32), perms[1].ctypes.data_as(_PI32))
+        return [perms[s][: self.nslots(s)] if n_before[s] else perms[s][:0] for s in range(2)]
+
+    def keys(self, s: int) -> np.ndarray:
+        k = np.zeros(max(1, self.nslots(s)), dtype=np.int32)
+        lib().orc_keys(self._h, s, k.ctypes.data_as(_PI32))
+        return k[: self.nslots(s)]
+
+    def nslots(self, s: int) -> int:
+        return lib().orc_nslots(self._h, s)
+
+    def nlive(self, s: int) -> int:
+        return lib().orc_nlive(self._h, s)
+
+    @property
+    def step_index(self) -> int:
+        return lib().orc_step_index(self._h)
+
+    @property
+    def acc_e(self) -> float:
+        return lib().orc_acc_e(self._h)
+
+    def absorbed_total(self, s: int) -> int:
+        return lib().orc_absorbed_total(self._h, s)
+
+    def injected_total(self, s: int) -> int:
+        return lib().orc_injected_total(self._h, s)
+
+    def particles(self, s: int):
+        n = self.nslots(s)
+        arrs = [np.zeros(max(1, n)) for _ in range(4)]
+        lib().orc_get_particles(self._h, s, *[_dp(a) for a in arrs])
+        return tuple(a[:n] for a in arrs)
+
+    def set_particles(self, s: int, x, vx, vy, vz):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, vx, vy, vz)]
+        n = len(arrs[0])
+        lib().orc_set_particles(self._h, s, n, *[_dp(a) for a in arrs])
+
+    def set_counters(self, step: int, acc_e: float):
+        lib().orc_set_counters(self._h, step, acc_e)
+
+    def grid(self):
+        nodes = self.nx + 1
+        Q0, Q1, phi, E = (np.zeros(nodes) for _ in range(4))
+        lib().orc_get_grid(self._h, _dp(Q0), _dp(Q1), _dp(phi), _dp(E))
+        return {"Q": np.stack([Q0, Q1]), "phi": phi, "E": E}
+
+    def moments(self) -> np.ndarray:
+        nodes = self.nx + 1
+        out = np.zeros((1 + 3 * self.nspecies) * nodes)
+        lib().orc_moments(self._h, _dp(out))
+        return out.reshape(1 + 3 * self.nspecies, nodes)
+
+    def wall_potential(self) -> float:
+        g = self.grid()
+        return float(g["phi"][0] - g["phi"][-1])
+
+    def weights(self):
+        return [weight(self.cfg, s) for s in range(self.nspecies)]
+
+
+def thermal_speed(cfg: dict, s: int) -> float:
+    sp = cfg["species"][s]
+    return math.sqrt(sp["temperature"] / sp["mass"])

@@ -1,0 +1,743 @@
+/*
+ * slpic_oracle.c -- FP64 CPU oracle for speed-limited PIC (SLPIC), 1D3V.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark.  Plain, slow and written to be checked by
+ * eye against the paper; it shares no code with the HIP library.
+ *
+ * Paper: Werner, Jenkins, Chap & Cary, arXiv:1511.08225.
+ *   Sec. II, Eq. (5)       f = beta g  (particles sample g, physical f is beta-weighted)
+ *   Sec. II, Eq. (10a,b)   dx/dt = beta v, dv/dt = beta a
+ *   Sec. II, Eq. (11a,b)   the two speed-limiting functions
+ *   Appendix, Eq. (A1a-d)  electrostatic SLPIC with beta(|v|)
+ *   Appendix, Eq. (A2a-d)  leapfrog discretisation; the integral of beta over
+ *                          the step in (A2a) is evaluated along the velocity
+ *                          path with E frozen at E^n(x^n)
+ *
+ * Readings where the paper is silent (identical on the GPU side, documented
+ * with the design):
+ *   - beta_step(|v| = v0) = 1;
+ *   - the integral of beta in (A2a) is evaluated exactly along the frozen-field
+ *     velocity characteristic (the converged limit of the paper's adaptive
+ *     modified-midpoint quadrature, which is available as ORC_KICK_MMP);
+ *   - cloud-in-cell weights, node-centred grid, half-volume end nodes,
+ *     symmetry plane at x = 0 (specular particles, dphi/dx = 0) and a grounded
+ *     absorbing wall at x = L (phi = 0);
+ *   - thermal source: pairs balanced by ion loss, uniform in
+ *     xt in [0, source_cells), Maxwellian velocity (the source term of g equals
+ *     the physical source term once the right-hand side of Eq. (7) is dropped);
+ *   - initial load samples g0 = f0/beta with weight dx*Z/ppc, Z = <1/beta>.
+ *
+ * Parity pins: see tests/test_oracle_*.py (closed forms, limits, brute force).
+ */
+#include "slpic_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TWO_PI 6.283185307179586
+#define SQRT_2_OVER_PI 0.7978845608028654
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from the definition in Salmon, Moraes, Dror & Shaw,        */
+/* "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two  */
+/* 32x32->64 multiplies with a Weyl-sequence key schedule.                   */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 53-bit uniform in [0,1) from two 32-bit words (27 + 26 bits). */
+double orc_u53(uint32_t a, uint32_t b) {
+    double hi = (double)(a >> 5);
+    double lo = (double)(b >> 6);
+    return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+/* A per-particle stream of uniforms: counter = (index, step, run, tag|sub);
+ * every Philox call yields two uniforms, sub counts the calls. */
+typedef struct {
+    uint32_t ctr[4];
+    uint32_t key[2];
+    uint32_t buf[4];
+    int pos;
+} orc_stream;
+
+static void stream_init(orc_stream* st, const orc_config* cfg, uint32_t index, uint32_t step,
+                        int purpose, int species) {
+    st->ctr[0] = index;
+    st->ctr[1] = step;
+    st->ctr[2] = (uint32_t)cfg->run;
+    st->ctr[3] = ((uint32_t)purpose << 24) | ((uint32_t)species << 20);
+    st->key[0] = (uint32_t)(cfg->seed & 0xffffffffu);
+    st->key[1] = (uint32_t)(cfg->seed >> 32);
+    st->pos = 4;
+}
+
+static double stream_next(orc_stream* st) {
+    if (st->pos >= 4) {
+        orc_philox4x32_10(st->ctr, st->key, st->buf);
+        st->ctr[3] += 1u;
+        st->pos = 0;
+    }
+    double u = orc_u53(st->buf[st->pos], st->buf[st->pos + 1]);
+    st->pos += 2;
+    return u;
+}
+
+/* Three independent standard normals by the Box-Muller transform. */
+static void stream_normal3(orc_stream* st, double z[3]) {
+    double u1 = stream_next(st);
+    double u2 = stream_next(st);
+    double r = sqrt(-2.0 * log(1.0 - u1));
+    double th = TWO_PI * u2;
+    z[0] = r * cos(th);
+    z[1] = r * sin(th);
+    double u3 = stream_next(st);
+    double u4 = stream_next(st);
+    double r2 = sqrt(-2.0 * log(1.0 - u3));
+    z[2] = r2 * cos(TWO_PI * u4);
+}
+
+/* ------------------------------------------------------------------------ */
+/* beta, Eq. (11a) and Eq. (11b).                                           */
+/* ------------------------------------------------------------------------ */
+static double beta_of_s2(int kind, double u, double s2) {
+    if (isinf(u)) return 1.0;
+    if (kind == ORC_BETA_SMOOTH) return 1.0 / sqrt(1.0 + s2 / (u * u)); /* Eq. (11a) */
+    /* Eq. (11b), with beta = 1 on the boundary |v| = v0 */
+    if (s2 <= u * u) return 1.0;
+    return u / sqrt(s2);
+}
+
+double orc_beta(int kind, double u, double speed) { return beta_of_s2(kind, u, speed * speed); }
+
+/* |v|^2 = vx^2 + (vy^2 + vz^2): the perpendicular part is a constant of the
+ * 1D motion, so it is summed first. */
+static double norm2(const double v[3]) { return v[0] * v[0] + (v[1] * v[1] + v[2] * v[2]); }
+
+/* ------------------------------------------------------------------------ */
+/* The velocity update of Eq. (A2a).                                        */
+/*                                                                          */
+/* With a = (q/m) E^n(x^n) frozen over the step, Eq. (A1b) moves v along    */
+/* the line through v parallel to a: write v = vperp + p ahat with c =      */
+/* |vperp| fixed; then dp/dt = |a| beta(sqrt(p^2 + c^2)).  Where beta = 1   */
+/* the motion is dp/dt = |a|.  Where beta = v0/|v| (Eq. 11b, fast) or       */
+/* v0/sqrt(|v|^2 + v0^2) (Eq. 11a, with c^2 -> c^2 + v0^2),                 */
+/*   sqrt(p^2 + c^2) dp = |a| v0 dt,                                        */
+/* whose antiderivative is G_c(p) = (p sqrt(p^2+c^2) + c^2 asinh(p/c))/2.   */
+/* The integral of beta over the step is then (p_end - p_start)/|a|.        */
+/* ------------------------------------------------------------------------ */
+double orc_G(double c2, double p) {
+    if (c2 == 0.0) return 0.5 * p * fabs(p);
+    double c = sqrt(c2);
+    return 0.5 * (p * sqrt(p * p + c2) + c2 * asinh(p / c));
+}
+
+/* p1 >= p0 with G_c(p1) - G_c(p0) = K (K >= 0): Newton on the monotone G,
+ * safeguarded by bisection inside a bracket.  Upper bounds: sqrt(p^2+c^2)
+ * >= |p| gives the c = 0 solution, sqrt(p^2+c^2) >= c gives p0 + K/c. */
+double orc_fast_advance(double c2, double p0, double K) {
+    if (!(K > 0.0)) return p0;
+    double Gt = orc_G(c2, p0) + K;
+    double Q = 0.5 * p0 * fabs(p0) + K;
+    double hi = (Q >= 0.0) ? sqrt(2.0 * Q) : -sqrt(-2.0 * Q);
+    if (c2 > 0.0) {
+        double hi2 = p0 + K / sqrt(c2);
+        if (hi2 < hi) hi = hi2;
+    }
+    double lo = p0;
+    double p = hi;
+    for (int it = 0; it < 400; ++it) {
+        double r = orc_G(c2, p) - Gt;
+        if (r == 0.0) return p;
+        if (r > 0.0) hi = p; else lo = p;
+        double s = sqrt(p * p + c2);
+        double pn = (s > 0.0) ? p - r / s : 0.5 * (lo + hi);
+        if (!(pn > lo && pn < hi)) pn = 0.5 * (lo + hi);
+        double scale = fmax(fabs(lo), fabs(hi));
+        if (fabs(pn - p) <= 4.0 * DBL_EPSILON * fabs(pn) || hi - lo <= 4.0 * DBL_EPSILON * scale)
+            return pn;
+        p = pn;
+    }
+    return p;
+}
+
+void orc_kick_exact(int kind, double u, double dt, const double v[3], const double a[3],
+                    double vout[3]) {
+    double A2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+    if (A2 == 0.0) {
+        vout[0] = v[0]; vout[1] = v[1]; vout[2] = v[2];
+        return;
+    }
+    if (isinf(u)) { /* beta == 1: standard leapfrog, Eq. (4) */
+        vout[0] = v[0] + a[0] * dt;
+        vout[1] = v[1] + a[1] * dt;
+        vout[2] = v[2] + a[2] * dt;
+        return;
+    }
+    double u2 = u * u;
+    if (kind == ORC_BETA_STEP && norm2(v) <= u2) {
+        /* |v|^2 is convex along the straight velocity path: if both ends of
+         * the unlimited trial step are inside the band, beta = 1 throughout */
+        double vt[3] = {v[0] + a[0] * dt, v[1] + a[1] * dt, v[2] + a[2] * dt};
+        if (norm2(vt) <= u2) {
+            vout[0] = vt[0]; vout[1] = vt[1]; vout[2] = vt[2];
+            return;
+        }
+    }
+    double A = sqrt(A2);
+    double ah[3] = {a[0] / A, a[1] / A, a[2] / A};
+    double p0 = v[0] * ah[0] + v[1] * ah[1] + v[2] * ah[2];
+    double vp[3] = {v[0] - p0 * ah[0], v[1] - p0 * ah[1], v[2] - p0 * ah[2]};
+    double c2 = vp[0] * vp[0] + (vp[1] * vp[1] + vp[2] * vp[2]);
+    double p1;
+    if (kind == ORC_BETA_SMOOTH) {
+        p1 = orc_fast_advance(c2 + u2, p0, A * u * dt);
+    } else if (c2 >= u2) {
+        p1 = orc_fast_advance(c2, p0, A * u * dt);
+    } else {
+        /* Eq. (11b): fast approaching the band, slow inside |p| <= ps, fast leaving */
+        double ps = sqrt(u2 - c2);
+        double p = p0;
+        double rem = dt;
+        int done = 0;
+        p1 = p0;
+        if (p < -ps) {
+            double Kneed = orc_G(c2, -ps) - orc_G(c2, p);
+            double Kav = A * u * rem;
+            if (Kneed >= Kav) {
+                p1 = orc_fast_advance(c2, p, Kav);
+                done = 1;
+            } else {
+                rem -= Kneed / (A * u);
+                p = -ps;
+            }
+        }
+        if (!done && p <= ps) {
+            double tb = (ps - p) / A;
+            if (tb >= rem) {
+                p1 = p + A * rem;
+                done = 1;
+            } else {
+                rem -= tb;
+                p = ps;
+            }
+        }
+        if (!done) p1 = orc_fast_advance(c2, p, A * u * rem);
+    }
+    vout[0] = vp[0] + ah[0] * p1;
+    vout[1] = vp[1] + ah[1] * p1;
+    vout[2] = vp[2] + ah[2] * p1;
+}
+
+/* The paper's own quadrature (Appendix): the modified midpoint method
+ * applied to dv/dt = beta(|v|) a, dI/dt = beta(|v|), with the number of
+ * substeps doubled until I (the integral of beta over the step) changes by
+ * at most tol relative; then v^{n+1/2} = v^{n-1/2} + a I as in Eq. (A2a).
+ * Returns the number of substeps used. */
+static void mmp_rhs(int kind, double u, const double a[3], const double y[4], double f[4]) {
+    double b = beta_of_s2(kind, u, norm2(y));
+    f[0] = b * a[0];
+    f[1] = b * a[1];
+    f[2] = b * a[2];
+    f[3] = b;
+}
+
+int orc_kick_mmp(int kind, double u, double dt, const double v[3], const double a[3], double tol,
+                 int nmax, double vout[3]) {
+    double y0[4] = {v[0], v[1], v[2], 0.0};
+    double prev = 0.0, I = 0.0;
+    int n;
+    for (n = 2; n <= nmax; n *= 2) {
+        double h = dt / n;
+        double z0[4], z1[4], z2[4], f[4];
+        memcpy(z0, y0, sizeof z0);
+        mmp_rhs(kind, u, a, z0, f);
+        for (int k = 0; k < 4; ++k) z1[k] = z0[k] + h * f[k];
+        for (int m = 1; m < n; ++m) {
+            mmp_rhs(kind, u, a, z1, f);
+            for (int k = 0; k < 4; ++k) z2[k] = z0[k] + 2.0 * h * f[k];
+            memcpy(z0, z1, sizeof z0);
+            memcpy(z1, z2, sizeof z1);
+        }
+        mmp_rhs(kind, u, a, z1, f);
+        I = 0.5 * (z1[3] + z0[3] + h * f[3]);
+        if (n > 2 && fabs(I - prev) <= tol * fabs(I)) break;
+        prev = I;
+    }
+    if (n > nmax) n = nmax;
+    vout[0] = v[0] + a[0] * I;
+    vout[1] = v[1] + a[1] * I;
+    vout[2] = v[2] + a[2] * I;
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Loading g0 = f0/beta (Eq. 5) and the thermal source.                      */
+/* ------------------------------------------------------------------------ */
+
+/* Maxwell speed density (units of vt): sqrt(2/pi) s^2 exp(-s^2/2). */
+static double maxwell_speed_pdf(double s) { return SQRT_2_OVER_PI * s * s * exp(-0.5 * s * s); }
+
+/* Z = <1/beta> over the Maxwellian.  Eq. (11b): closed form from the split
+ * at s = ut (slow part is the Maxwell mass below ut, fast part integrates
+ * s/ut times the density).  Eq. (11a): Simpson quadrature of
+ * sqrt(1 + s^2/ut^2) against the Maxwell speed density. */
+static void step_mixture(double ut, double* Ps, double* Pf) {
+    double e = exp(-0.5 * ut * ut);
+    *Ps = erf(ut / sqrt(2.0)) - SQRT_2_OVER_PI * ut * e;
+    *Pf = SQRT_2_OVER_PI * (ut * ut + 2.0) * e / ut;
+}
+
+double orc_Z(int kind, double ut) {
+    if (isinf(ut)) return 1.0;
+    if (kind == ORC_BETA_STEP) {
+        double Ps, Pf;
+        step_mixture(ut, &Ps, &Pf);
+        return Ps + Pf;
+    }
+    const int n = 1 << 17;
+    const double smax = 48.0;
+    double h = smax / n, sum = 0.0;
+    for (int k = 0; k <= n; ++k) {
+        double s = k * h;
+        double fk = maxwell_speed_pdf(s) * sqrt(1.0 + (s / ut) * (s / ut));
+        double wk = (k == 0 || k == n) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+        sum += wk * fk;
+    }
+    return sum * h / 3.0;
+}
+
+static double species_vt(const orc_config* cfg, int s) {
+    return sqrt(cfg->species[s].temperature / cfg->species[s].mass);
+}
+
+double orc_weight(const orc_config* cfg, int s) {
+    double ut = cfg->u / species_vt(cfg, s);
+    return cfg->dx * orc_Z(cfg->beta_kind, ut) / (double)cfg->species[s].ppc;
+}
+
+/* speed (units of vt) from the g-speed density of Eq. (11b):
+ * proportional to s^2 e^{-s^2/2} max(1, s/ut) */
+static double sample_g_speed_step(orc_stream* st, double ut) {
+    double Ps, Pf;
+    step_mixture(ut, &Ps, &Pf);
+    double usel = stream_next(st);
+    if (usel * (Ps + Pf) < Ps) {
+        for (int attempt = 0; attempt < 100000; ++attempt) {
+            if (ut <= 1.0) {
+                double s = ut * cbrt(stream_next(st));
+                double acc = stream_next(st);
+                if (acc < exp(-0.5 * s * s)) return s;
+            } else {
+                double z[3];
+                stream_normal3(st, z);
+                double s = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+                if (s <= ut) return s;
+            }
+        }
+        return 0.0;
+    }
+    /* s^3 e^{-s^2/2} on s > ut: with t = s^2/2, density (t0 + y) e^{-y},
+     * y = t - t0 >= 0: an Exp(1) / Gamma(2) mixture with weights t0 : 1 */
+    double t0 = 0.5 * ut * ut;
+    double uc = stream_next(st);
+    double y = -log(1.0 - stream_next(st));
+    if (!(uc * (t0 + 1.0) < t0)) {
+        double y2 = -log(1.0 - stream_next(st));
+        y += y2;
+    }
+    return sqrt(2.0 * (t0 + y));
+}
+
+static double sample_g_speed(orc_stream* st, int kind, double ut) {
+    if (kind == ORC_BETA_STEP) return sample_g_speed_step(st, ut);
+    /* Eq. (11a): rejection from the Eq. (11b) g-density; the ratio
+     * sqrt(1 + s^2/ut^2) / max(1, s/ut) lies in [1, sqrt 2] */
+    for (int attempt = 0; attempt < 100000; ++attempt) {
+        double s = sample_g_speed_step(st, ut);
+        double r = sqrt(1.0 + (s / ut) * (s / ut)) / (sqrt(2.0) * fmax(1.0, s / ut));
+        if (stream_next(st) < r) return s;
+    }
+    return 0.0;
+}
+
+void orc_load_particle(const orc_config* cfg, int s, uint32_t i, double out[4]) {
+    orc_stream st;
+    stream_init(&st, cfg, i, 0u, ORC_PURPOSE_LOAD, s);
+    double vt = species_vt(cfg, s);
+    out[0] = (double)cfg->nx * stream_next(&st);
+    if (isinf(cfg->u)) {
+        double z[3];
+        stream_normal3(&st, z);
+        out[1] = vt * z[0]; out[2] = vt * z[1]; out[3] = vt * z[2];
+        return;
+    }
+    double sp = sample_g_speed(&st, cfg->beta_kind, cfg->u / vt);
+    double mu = 2.0 * stream_next(&st) - 1.0;
+    double ph = TWO_PI * stream_next(&st);
+    double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+    out[1] = vt * sp * mu;
+    out[2] = vt * sp * (sn * cos(ph));
+    out[3] = vt * sp * (sn * sin(ph));
+}
+
+void orc_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step, double out[4]) {
+    orc_stream st;
+    stream_init(&st, cfg, k, step, ORC_PURPOSE_INJECT, s);
+    double vt = species_vt(cfg, s);
+    out[0] = (double)cfg->source_cells * stream_next(&st);
+    double z[3];
+    stream_normal3(&st, z);
+    out[1] = vt * z[0]; out[2] = vt * z[1]; out[3] = vt * z[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Poisson, Eq. (A2d) with eps0 = 1: -phi'' = rho on nodes 0..nx.            */
+/* Node 0: symmetry plane, -2(phi1 - phi0)/dx^2 = rho0; node nx: phi = 0.    */
+/* rho_j = Q_j / dV_j with dV = dx inside and dx/2 at both end nodes.       */
+/* Solved by the Thomas algorithm; E by centred differences, E_0 = 0 and a  */
+/* one-sided second-order difference at the wall.                           */
+/* ------------------------------------------------------------------------ */
+void orc_poisson1d(int32_t nx, double dx, const double* Q, double* phi, double* E) {
+    int n = nx; /* unknowns phi_0..phi_{nx-1} */
+    double* cp = (double*)malloc(sizeof(double) * (size_t)n);
+    double* dp = (double*)malloc(sizeof(double) * (size_t)n);
+    double dx2 = dx * dx;
+    for (int j = 0; j < n; ++j) {
+        double dV = (j == 0) ? 0.5 * dx : dx;
+        double rhs = (Q[j] / dV) * dx2;
+        double aj = (j == 0) ? 0.0 : -1.0;
+        double bj = 2.0;
+        double cj = (j == 0) ? -2.0 : -1.0;
+        if (j == 0) {
+            cp[0] = cj / bj;
+            dp[0] = rhs / bj;
+        } else {
+            double m = bj - aj * cp[j - 1];
+            cp[j] = cj / m;
+            dp[j] = (rhs - aj * dp[j - 1]) / m;
+        }
+    }
+    phi[nx] = 0.0;
+    phi[n - 1] = dp[n - 1];
+    for (int j = n - 2; j >= 0; --j) phi[j] = dp[j] - cp[j] * phi[j + 1];
+    E[0] = 0.0;
+    for (int j = 1; j < nx; ++j) E[j] = -(phi[j + 1] - phi[j - 1]) / (2.0 * dx);
+    E[nx] = -(3.0 * phi[nx] - 4.0 * phi[nx - 1] + phi[nx - 2]) / (2.0 * dx);
+    free(cp);
+    free(dp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* A run: particle slots (dead slots have xt < 0 until compaction), grids.   */
+/* ------------------------------------------------------------------------ */
+struct orc_run {
+    orc_config cfg;
+    double w[2], qw[2], qm[2], vt[2];
+    int64_t n[2], cap[2];
+    double *x[2], *vx[2], *vy[2], *vz[2];
+    double *Q[2], *phi, *E;
+    double acc_e;
+    int64_t step;
+    int64_t absorbed_total[2], injected_total[2];
+};
+
+static void ensure_capacity(orc_run* r, int s, int64_t need) {
+    if (need <= r->cap[s]) return;
+    int64_t cap = r->cap[s] > 0 ? r->cap[s] : 16;
+    while (cap < need) cap *= 2;
+    r->x[s] = (double*)realloc(r->x[s], sizeof(double) * (size_t)cap);
+    r->vx[s] = (double*)realloc(r->vx[s], sizeof(double) * (size_t)cap);
+    r->vy[s] = (double*)realloc(r->vy[s], sizeof(double) * (size_t)cap);
+    r->vz[s] = (double*)realloc(r->vz[s], sizeof(double) * (size_t)cap);
+    r->cap[s] = cap;
+}
+
+orc_run* orc_create(const orc_config* cfg) {
+    orc_run* r = (orc_run*)calloc(1, sizeof(orc_run));
+    r->cfg = *cfg;
+    int nodes = cfg->nx + 1;
+    for (int s = 0; s < cfg->nspecies; ++s) {
+        r->vt[s] = species_vt(cfg, s);
+        r->w[s] = orc_weight(cfg, s);
+        r->qw[s] = cfg->species[s].charge * r->w[s];
+        r->qm[s] = cfg->species[s].charge / cfg->species[s].mass;
+        r->Q[s] = (double*)calloc((size_t)nodes, sizeof(double));
+        int64_t n0 = (int64_t)cfg->nx * cfg->species[s].ppc;
+        double cf = cfg->capacity_factor > 1.0 ? cfg->capacity_factor : 1.0;
+        ensure_capacity(r, s, (int64_t)ceil(cf * (double)n0) + 1);
+    }
+    r->phi = (double*)calloc((size_t)nodes, sizeof(double));
+    r->E = (double*)calloc((size_t)nodes, sizeof(double));
+    return r;
+}
+
+void orc_destroy(orc_run* r) {
+    if (!r) return;
+    for (int s = 0; s < 2; ++s) {
+        free(r->x[s]); free(r->vx[s]); free(r->vy[s]); free(r->vz[s]); free(r->Q[s]);
+    }
+    free(r->phi);
+    free(r->E);
+    free(r);
+}
+
+/* Eq. (A2c): Q_j = sum_p q w beta(|v^{n+1/2}|) W_j(x^{n+1}) with CIC W. */
+static void deposit(orc_run* r) {
+    int nodes = r->cfg.nx + 1;
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        memset(r->Q[s], 0, sizeof(double) * (size_t)nodes);
+        for (int64_t i = 0; i < r->n[s]; ++i) {
+            double xt = r->x[s][i];
+            if (xt < 0.0) continue;
+            double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+            double b = beta_of_s2(r->cfg.beta_kind, r->cfg.u, norm2(v));
+            int c = (int)floor(xt);
+            double f = xt - (double)c;
+            double wb = r->qw[s] * b;
+            r->Q[s][c] += wb * (1.0 - f);
+            r->Q[s][c + 1] += wb * f;
+        }
+    }
+}
+
+static void solve_fields(orc_run* r) {
+    int nodes = r->cfg.nx + 1;
+    double* Qt = (double*)calloc((size_t)nodes, sizeof(double));
+    for (int j = 0; j < nodes; ++j)
+        for (int s = 0; s < r->cfg.nspecies; ++s) Qt[j] += r->Q[s][j];
+    orc_poisson1d(r->cfg.nx, r->cfg.dx, Qt, r->phi, r->E);
+    free(Qt);
+}
+
+void orc_refresh_fields(orc_run* r) {
+    deposit(r);
+    solve_fields(r);
+}
+
+void orc_keys(const orc_run* r, int32_t s, int32_t* keys) {
+    int b = r->cfg.sort_bucket;
+    for (int64_t i = 0; i < r->n[s]; ++i) {
+        double xt = r->x[s][i];
+        if (xt < 0.0) keys[i] = -1;
+        else keys[i] = (b > 0) ? (int32_t)floor(xt) / b : 0;
+    }
+}
+
+/* Stable counting sort by key, dead slots dropped; perm[new] = old. */
+void orc_sort(orc_run* r, int32_t* perm0, int32_t* perm1) {
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        int64_t n = r->n[s];
+        int32_t* keys = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        orc_keys(r, s, keys);
+        int nkeys = (r->cfg.sort_bucket > 0) ? (r->cfg.nx + r->cfg.sort_bucket - 1) / r->cfg.sort_bucket : 1;
+        int64_t* start = (int64_t*)calloc((size_t)nkeys + 1, sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i)
+            if (keys[i] >= 0) start[keys[i] + 1] += 1;
+        for (int k = 0; k < nkeys; ++k) start[k + 1] += start[k];
+        int64_t nlive = start[nkeys];
+        double* nx_ = (double*)malloc(sizeof(double) * (size_t)(nlive + 1));
+        double* nvx = (double*)malloc(sizeof(double) * (size_t)(nlive + 1));
+        double* nvy = (double*)malloc(sizeof(double) * (size_t)(nlive + 1));
+        double* nvz = (double*)malloc(sizeof(double) * (size_t)(nlive + 1));
+        int32_t* perm = (s == 0) ? perm0 : perm1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (keys[i] < 0) continue;
+            int64_t d = start[keys[i]]++;
+            nx_[d] = r->x[s][i];
+            nvx[d] = r->vx[s][i];
+            nvy[d] = r->vy[s][i];
+            nvz[d] = r->vz[s][i];
+            if (perm) perm[d] = (int32_t)i;
+        }
+        memcpy(r->x[s], nx_, sizeof(double) * (size_t)nlive);
+        memcpy(r->vx[s], nvx, sizeof(double) * (size_t)nlive);
+        memcpy(r->vy[s], nvy, sizeof(double) * (size_t)nlive);
+        memcpy(r->vz[s], nvz, sizeof(double) * (size_t)nlive);
+        r->n[s] = nlive;
+        free(nx_); free(nvx); free(nvy); free(nvz); free(start); free(keys);
+    }
+}
+
+void orc_load(orc_run* r) {
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        int64_t n0 = (int64_t)r->cfg.nx * r->cfg.species[s].ppc;
+        ensure_capacity(r, s, n0);
+        for (int64_t i = 0; i < n0; ++i) {
+            double p[4];
+            orc_load_particle(&r->cfg, s, (uint32_t)i, p);
+            r->x[s][i] = p[0]; r->vx[s][i] = p[1]; r->vy[s][i] = p[2]; r->vz[s][i] = p[3];
+        }
+        r->n[s] = n0;
+    }
+    r->step = 0;
+    r->acc_e = 0.0;
+    if (r->cfg.sort_every > 0) orc_sort(r, NULL, NULL);
+    orc_refresh_fields(r);
+}
+
+static void inject(orc_run* r, int s, int64_t count) {
+    ensure_capacity(r, s, r->n[s] + count);
+    for (int64_t k = 0; k < count; ++k) {
+        double p[4];
+        orc_inject_particle(&r->cfg, s, (uint32_t)k, (uint32_t)r->step, p);
+        int64_t i = r->n[s] + k;
+        r->x[s][i] = p[0]; r->vx[s][i] = p[1]; r->vy[s][i] = p[2]; r->vz[s][i] = p[3];
+    }
+    r->n[s] += count;
+    r->injected_total[s] += count;
+}
+
+/* One step of Eq. (A2a-d). */
+void orc_step(orc_run* r, int32_t nsteps) {
+    const orc_config* cfg = &r->cfg;
+    double dtdx = cfg->dt / cfg->dx;
+    for (int32_t it = 0; it < nsteps; ++it) {
+        int64_t absorbed[2] = {0, 0};
+        for (int s = 0; s < cfg->nspecies; ++s) {
+            for (int64_t i = 0; i < r->n[s]; ++i) {
+                double xt = r->x[s][i];
+                if (xt < 0.0) continue;
+                /* gather E^n(x^n), CIC */
+                int c = (int)floor(xt);
+                double f = xt - (double)c;
+                double Ex = r->E[c] * (1.0 - f) + r->E[c + 1] * f;
+                double a[3] = {r->qm[s] * Ex, 0.0, 0.0};
+                double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+                double v1[3];
+                if (cfg->kick == ORC_KICK_MMP)
+                    orc_kick_mmp(cfg->beta_kind, cfg->u, cfg->dt, v, a, cfg->mmp_tol, 1 << 20, v1);
+                else
+                    orc_kick_exact(cfg->beta_kind, cfg->u, cfg->dt, v, a, v1);
+                /* Eq. (A2b): x^{n+1} = x^n + beta(|v^{n+1/2}|) v^{n+1/2} dt */
+                double b = beta_of_s2(cfg->beta_kind, cfg->u, norm2(v1));
+                double xn = xt + b * v1[0] * dtdx;
+                if (xn < 0.0) { /* symmetry plane: specular reflection */
+                    xn = -xn;
+                    v1[0] = -v1[0];
+                }
+                r->vx[s][i] = v1[0];
+                r->vy[s][i] = v1[1];
+                r->vz[s][i] = v1[2];
+                if (xn >= (double)cfg->nx) { /* absorbing wall */
+                    r->x[s][i] = -1.0;
+                    absorbed[s] += 1;
+                } else {
+                    r->x[s][i] = xn;
+                }
+            }
+            r->absorbed_total[s] += absorbed[s];
+        }
+        /* thermal source: ion-loss-balanced pairs */
+        if (cfg->nspecies == 2) {
+            int64_t ni = absorbed[1];
+            r->acc_e += (double)ni * (r->w[1] / r->w[0]);
+            int64_t ne = (int64_t)floor(r->acc_e);
+            r->acc_e -= (double)ne;
+            inject(r, 1, ni);
+            inject(r, 0, ne);
+        }
+        deposit(r);
+        solve_fields(r);
+        r->step += 1;
+        if (cfg->sort_every > 0 && r->step % cfg->sort_every == 0) orc_sort(r, NULL, NULL);
+    }
+}
+
+/* beta-weighted moments at nodes: phi, then per species density n,
+ * flux Gamma_x = sum w beta vx W / dV and kinetic energy density
+ * sum w beta (m |v|^2 / 2) W / dV (f = beta g, Eq. 5). */
+void orc_moments(const orc_run* r, double* out) {
+    int nodes = r->cfg.nx + 1;
+    int ns = r->cfg.nspecies;
+    memset(out, 0, sizeof(double) * (size_t)(nodes * (1 + 3 * ns)));
+    memcpy(out, r->phi, sizeof(double) * (size_t)nodes);
+    for (int s = 0; s < ns; ++s) {
+        double* n = out + (size_t)nodes * (1 + 3 * s);
+        double* G = n + nodes;
+        double* K = G + nodes;
+        for (int64_t i = 0; i < r->n[s]; ++i) {
+            double xt = r->x[s][i];
+            if (xt < 0.0) continue;
+            double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+            double v2 = norm2(v);
+            double wb = r->w[s] * beta_of_s2(r->cfg.beta_kind, r->cfg.u, v2);
+            int c = (int)floor(xt);
+            double f = xt - (double)c;
+            double w0 = wb * (1.0 - f), w1 = wb * f;
+            double ke = 0.5 * r->cfg.species[s].mass * v2;
+            n[c] += w0; n[c + 1] += w1;
+            G[c] += w0 * v[0]; G[c + 1] += w1 * v[0];
+            K[c] += w0 * ke; K[c + 1] += w1 * ke;
+        }
+        for (int j = 0; j < nodes; ++j) {
+            double dV = (j == 0 || j == nodes - 1) ? 0.5 * r->cfg.dx : r->cfg.dx;
+            n[j] /= dV; G[j] /= dV; K[j] /= dV;
+        }
+    }
+}
+
+int64_t orc_nslots(const orc_run* r, int32_t s) { return r->n[s]; }
+int64_t orc_capacity(const orc_run* r, int32_t s) { return r->cap[s]; }
+int64_t orc_nlive(const orc_run* r, int32_t s) {
+    int64_t k = 0;
+    for (int64_t i = 0; i < r->n[s]; ++i) k += (r->x[s][i] >= 0.0);
+    return k;
+}
+int64_t orc_step_index(const orc_run* r) { return r->step; }
+double orc_acc_e(const orc_run* r) { return r->acc_e; }
+int64_t orc_absorbed_total(const orc_run* r, int32_t s) { return r->absorbed_total[s]; }
+int64_t orc_injected_total(const orc_run* r, int32_t s) { return r->injected_total[s]; }
+
+void orc_get_particles(const orc_run* r, int32_t s, double* x, double* vx, double* vy, double* vz) {
+    size_t n = (size_t)r->n[s];
+    memcpy(x, r->x[s], n * sizeof(double));
+    memcpy(vx, r->vx[s], n * sizeof(double));
+    memcpy(vy, r->vy[s], n * sizeof(double));
+    memcpy(vz, r->vz[s], n * sizeof(double));
+}
+
+int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const double* vx,
+                      const double* vy, const double* vz) {
+    ensure_capacity(r, s, n);
+    memcpy(r->x[s], x, (size_t)n * sizeof(double));
+    memcpy(r->vx[s], vx, (size_t)n * sizeof(double));
+    memcpy(r->vy[s], vy, (size_t)n * sizeof(double));
+    memcpy(r->vz[s], vz, (size_t)n * sizeof(double));
+    r->n[s] = n;
+    return 0;
+}
+
+void orc_set_counters(orc_run* r, int64_t step, double acc_e) {
+    r->step = step;
+    r->acc_e = acc_e;
+}
+
+void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E) {
+    size_t nodes = (size_t)r->cfg.nx + 1;
+    if (Q0) memcpy(Q0, r->Q[0], nodes * sizeof(double));
+    if (Q1 && r->cfg.nspecies > 1) memcpy(Q1, r->Q[1], nodes * sizeof(double));
+    if (phi) memcpy(phi, r->phi, nodes * sizeof(double));
+    if (E) memcpy(E, r->E, nodes * sizeof(double));
+}

@@ -1,0 +1,107 @@
+/*
+ * slpic_oracle.h -- FP64 CPU oracle for speed-limited PIC (SLPIC).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and oracle/slpic_oracle.c are the
+ * plain, slow reference that the GPU path is checked against.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no code, header, table or constant generator with the HIP
+ * library, and the HIP library never calls it.
+ *
+ * Method (Werner, Jenkins, Chap & Cary, "Speeding Up Simulations By Slowing
+ * Down Particles: Speed-Limited Particle-in-Cell Simulation"):
+ *   - speed-limited equations of motion, Eq. (10a,b) and Appendix Eq. (A1a,b);
+ *   - beta functions, Eq. (11a) (smooth) and Eq. (11b) (step, default);
+ *   - leapfrog discretisation with the time integral of beta, Eq. (A2a-d);
+ *   - beta-weighted charge deposit, Eq. (A1c)/(A2c);
+ *   - Poisson solve, Eq. (A1d)/(A2d).
+ *
+ * Normalised units: x in electron Debye lengths, t in 1/omega_pe, v in the
+ * electron thermal speed, phi in T_e/e, density in n0; eps0 = e = m_e = 1.
+ * Positions are stored in grid units xt = x/dx.
+ */
+#ifndef SLPIC_ORACLE_H
+#define SLPIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BETA_STEP = 0, ORC_BETA_SMOOTH = 1 };
+enum { ORC_KICK_EXACT = 0, ORC_KICK_MMP = 1 };
+enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2 };
+
+typedef struct {
+    double charge, mass, temperature;
+    int32_t ppc;
+    int32_t pad;
+} orc_species;
+
+typedef struct {
+    int32_t nx;            /* cells; nodes are 0..nx, wall at node nx        */
+    int32_t beta_kind;     /* ORC_BETA_STEP / ORC_BETA_SMOOTH                */
+    double dx, dt, u;      /* u = +INFINITY -> standard PIC                  */
+    int32_t nspecies;      /* 2: species 0 electrons, species 1 ions         */
+    int32_t source_cells;  /* injection region xt in [0, source_cells)       */
+    orc_species species[2];
+    uint64_t seed;
+    int32_t run;           /* run index (enters the RNG counter)             */
+    int32_t sort_every;    /* 0: never compact; k: stable sort every k steps */
+    int32_t sort_bucket;   /* key = cell / bucket; <= 0: key 0 (compaction)  */
+    int32_t kick;          /* ORC_KICK_EXACT / ORC_KICK_MMP                  */
+    double mmp_tol;        /* relative tolerance of the modified midpoint    */
+    double capacity_factor;
+} orc_config;
+
+typedef struct orc_run orc_run;
+
+/* --- Philox4x32-10 counter-based generator (Salmon et al., SC'11) ------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u53(uint32_t a, uint32_t b);
+
+/* --- beta and the velocity map ----------------------------------------- */
+double orc_beta(int kind, double u, double speed);
+double orc_G(double c2, double p);
+double orc_fast_advance(double c2, double p0, double K);
+void orc_kick_exact(int kind, double u, double dt, const double v[3],
+                    const double a[3], double vout[3]);
+int orc_kick_mmp(int kind, double u, double dt, const double v[3],
+                 const double a[3], double tol, int nmax, double vout[3]);
+
+/* --- loading helpers ---------------------------------------------------- */
+double orc_Z(int kind, double u_over_vt);
+double orc_weight(const orc_config* cfg, int s);
+void orc_load_particle(const orc_config* cfg, int s, uint32_t i, double out[4]);
+void orc_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step, double out[4]);
+
+/* --- grid ---------------------------------------------------------------- */
+void orc_poisson1d(int32_t nx, double dx, const double* Q, double* phi, double* E);
+
+/* --- run ----------------------------------------------------------------- */
+orc_run* orc_create(const orc_config* cfg);
+void orc_destroy(orc_run* r);
+void orc_load(orc_run* r);
+void orc_refresh_fields(orc_run* r);
+void orc_step(orc_run* r, int32_t nsteps);
+void orc_sort(orc_run* r, int32_t* perm0, int32_t* perm1);
+void orc_keys(const orc_run* r, int32_t s, int32_t* keys);
+void orc_moments(const orc_run* r, double* out);
+
+int64_t orc_nslots(const orc_run* r, int32_t s);
+int64_t orc_capacity(const orc_run* r, int32_t s);
+int64_t orc_nlive(const orc_run* r, int32_t s);
+int64_t orc_step_index(const orc_run* r);
+double orc_acc_e(const orc_run* r);
+int64_t orc_absorbed_total(const orc_run* r, int32_t s);
+int64_t orc_injected_total(const orc_run* r, int32_t s);
+void orc_get_particles(const orc_run* r, int32_t s, double* x, double* vx, double* vy, double* vz);
+int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const double* vx,
+                      const double* vy, const double* vz);
+void orc_set_counters(orc_run* r, int64_t step, double acc_e);
+void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,105 @@
+"""Seeded synthetic workloads for the SLPIC sheath (parameters only).
+
+This module holds the problem definitions that both the CPU oracle and the
+HIP path are run on: grid sizes, species, temperatures, speed limits, time
+steps and seeds.  It contains none of the method's arithmetic (no push, no
+deposit, no field solve, no sampling); the random numbers the method draws
+come from the Philox generator each side implements from its published
+definition, keyed by the ``seed`` here.
+
+Normalised units: x in electron Debye lengths, t in 1/omega_pe, v in the
+electron thermal speed sqrt(T_e/m_e), energies in T_e; e = m_e = eps0 = 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+AMU_IN_ME = 1822.888486  # atomic mass unit in electron masses
+
+
+def species(te_over_ti: float, ion_amu: float, ppc: int):
+    """Electrons (species 0) and singly charged ions (species 1)."""
+    return [
+        {"charge": -1.0, "mass": 1.0, "temperature": 1.0, "ppc": int(ppc)},
+        {"charge": 1.0, "mass": ion_amu * AMU_IN_ME, "temperature": 1.0 / te_over_ti,
+         "ppc": int(ppc)},
+    ]
+
+
+def ion_thermal_speed(te_over_ti: float, ion_amu: float) -> float:
+    return math.sqrt((1.0 / te_over_ti) / (ion_amu * AMU_IN_ME))
+
+
+def sheath(nx: int, ppc: int, u_over_vti: float, dt: float | None = None, te_over_ti: float = 20.0,
+           ion_amu: float = 40.0, dx: float = 0.5, seed: int = 0, run: int = 0,
+           beta_kind: str = "step", sort_every: int = 1, sort_bucket: int = 1,
+           capacity_factor: float = 1.5, source_cells: int = 4) -> dict:
+    """A 1D3V sheath: symmetry plane at x = 0, grounded absorbing wall at
+    x = nx*dx, thermal source in the first ``source_cells`` cells.
+
+    Default time step: dt = min(dx/u, 1/omega_pi) for a finite speed limit
+    (the paper's dt = dx/v0 capped so that unlimited ions keep
+    omega_pi dt <= 1); dx/(5 v_te) for u = inf (the paper's PIC step)."""
+    vti = ion_thermal_speed(te_over_ti, ion_amu)
+    u = math.inf if math.isinf(u_over_vti) else u_over_vti * vti
+    if dt is None:
+        if math.isinf(u):
+            dt = dx / 5.0
+        else:
+            inv_wpi = math.sqrt(ion_amu * AMU_IN_ME)
+            dt = min(dx / u, inv_wpi)
+    return {
+        "nx": int(nx), "dx": float(dx), "dt": float(dt), "u": float(u), "beta_kind": beta_kind,
+        "species": species(te_over_ti, ion_amu, ppc), "source_cells": int(source_cells),
+        "seed": int(seed), "run": int(run), "sort_every": int(sort_every),
+        "sort_bucket": int(sort_bucket), "capacity_factor": float(capacity_factor),
+        "te_over_ti": float(te_over_ti), "ion_amu": float(ion_amu), "u_over_vti": float(u_over_vti),
+    }
+
+
+def small_sheath(seed: int = 0, **kw) -> dict:
+    """64 cells over 32 Debye lengths, argon, Te = 1 eV, Ti = 0.05 eV,
+    100 macroparticles per cell per species, u = 3 v_ti, dt = 5/omega_pe,
+    1000 steps (FP64)."""
+    kw.setdefault("ppc", 100)
+    return sheath(nx=64, u_over_vti=3.0, dt=5.0, te_over_ti=20.0, ion_amu=40.0, seed=seed, **kw)
+
+
+SMALL_SHEATH_STEPS = 1000
+
+
+def production_sheath(u_over_vti: float = 2.0, ppc: int = 1000, seed: int = 0, **kw) -> dict:
+    """2048 cells over 1024 Debye lengths, argon, Te = 1 eV, Ti = 0.05 eV,
+    1000 macroparticles per cell per species (4,096,000 particles),
+    u in {2, 5, 10, inf} v_ti, FP32 particles with FP64 grids."""
+    return sheath(nx=2048, ppc=ppc, u_over_vti=u_over_vti, te_over_ti=20.0, ion_amu=40.0,
+                  seed=seed, **kw)
+
+
+PRODUCTION_U_SWEEP = (2.0, 5.0, 10.0, math.inf)
+
+
+def batched_sweep(nruns: int = 256, seed: int = 1, ppc_range=(200, 1000), cells_range=(128, 2048),
+                  **kw) -> list[dict]:
+    """Independent 1D sheaths: cells uniform in [128, 2048], ppc uniform in
+    [200, 1000], Te/Ti log-uniform in [5, 100], ion mass in {4, 20, 40, 84}
+    amu, u uniform in [2, 10] v_ti; dx = 0.5 so L/lambda_D = cells/2."""
+    rng = np.random.default_rng(seed)
+    runs = []
+    for r in range(nruns):
+        nx = int(rng.integers(cells_range[0], cells_range[1] + 1))
+        ppc = int(rng.integers(ppc_range[0], ppc_range[1] + 1))
+        te_ti = float(math.exp(rng.uniform(math.log(5.0), math.log(100.0))))
+        amu = float(rng.choice([4.0, 20.0, 40.0, 84.0]))
+        k = float(rng.uniform(2.0, 10.0))
+        runs.append(sheath(nx=nx, ppc=ppc, u_over_vti=k, te_over_ti=te_ti, ion_amu=amu,
+                           seed=seed * 100003 + r, run=r, **kw))
+    return runs
+
+
+def features(cfg: dict) -> np.ndarray:
+    """Warm-start network inputs: (ln Te/Ti, ln A, u/v_ti, ln L/lambda_D)."""
+    return np.array([math.log(cfg["te_over_ti"]), math.log(cfg["ion_amu"]), cfg["u_over_vti"],
+                     math.log(cfg["nx"] * cfg["dx"])], dtype=np.float64)
