@@ -387,6 +387,7 @@ void orc_load_particle(const orc_config* cfg, int s, uint32_t i, double out[4]) 
     stream_init(&st, cfg, i, 0u, ORC_PURPOSE_LOAD, s);
     double vt = species_vt(cfg, s);
     out[0] = (double)cfg->nx * stream_next(&st);
+    if (out[0] >= (double)cfg->nx) out[0] = nextafter((double)cfg->nx, 0.0); /* rounding onto the wall */
     if (isinf(cfg->u)) {
         double z[3];
         stream_normal3(&st, z);
@@ -407,6 +408,7 @@ void orc_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step
     stream_init(&st, cfg, k, step, ORC_PURPOSE_INJECT, s);
     double vt = species_vt(cfg, s);
     out[0] = (double)cfg->source_cells * stream_next(&st);
+    if (out[0] >= (double)cfg->source_cells) out[0] = nextafter((double)cfg->source_cells, 0.0);
     double z[3];
     stream_normal3(&st, z);
     out[1] = vt * z[0]; out[2] = vt * z[1]; out[3] = vt * z[2];
