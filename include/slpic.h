@@ -1,0 +1,200 @@
+/*
+ * slpic.h -- C ABI of the MI355X (gfx950) speed-limited PIC library.
+ *
+ * Method: Werner, Jenkins, Chap & Cary, "Speeding Up Simulations By Slowing
+ * Down Particles: Speed-Limited Particle-in-Cell Simulation" (arXiv:1511.08225).
+ *   Eq. (5)        f = beta g: macroparticles sample g; the physical density
+ *                  is the beta-weighted sum over them.
+ *   Eq. (10a,b)    dx/dt = beta v, dv/dt = beta a.
+ *   Eq. (11a,b)    speed-limiting functions (smooth and step).
+ *   Appendix A,    electrostatic SLPIC and its leapfrog discretisation, which
+ *   Eq. (A1),(A2)  every step of this library implements: gather E^n(x^n),
+ *                  v^{n+1/2} = v^{n-1/2} + (q/m) E^n int beta dt, x^{n+1} =
+ *                  x^n + beta v^{n+1/2} dt, rho^{n+1} = sum w beta delta,
+ *                  div E^{n+1} = rho^{n+1}.
+ *
+ * Geometry (1D3V electrostatic sheath): x in [0, L = nx*dx]; x = 0 is a
+ * symmetry plane (specular particles, dphi/dx = 0), x = L a grounded
+ * absorbing wall (phi = 0).  A thermal source injects electron/ion pairs in
+ * the first source_cells cells, balancing the ion loss to the wall.
+ * Normalised units: x in electron Debye lengths, t in 1/omega_pe, v in the
+ * electron thermal speed, phi in T_e/e, density in n0; e = m_e = eps0 = 1.
+ *
+ * Memory and ownership.  The caller owns all device memory: one workspace of
+ * slpic_workspace_bytes() bytes (256-byte aligned device pointer), plus the
+ * output buffers passed to slpic_moments().  The library never allocates
+ * device memory.  It owns only the host-side context and the HIP graphs and
+ * events it creates, released by slpic_destroy().  "stream" arguments are
+ * hipStream_t handles passed as void* (NULL = the default stream).
+ *
+ * Errors.  Every int-returning call returns SLPIC_OK (0) or a negative
+ * SLPIC_E* code and never throws.  Faults found on the device (capacity
+ * overflow, non-finite particle velocities) set sticky per-run flags that
+ * slpic_status_query() reports; the affected particles are dropped and the
+ * run keeps stepping.
+ *
+ * Threading.  One context is used by one host thread at a time.  Work is
+ * enqueued on the stream given to each call; calls documented as "sync"
+ * synchronise that stream before returning.
+ */
+#ifndef SLPIC_H
+#define SLPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SLPIC_OK = 0,
+    SLPIC_EINVAL = -1,     /* bad argument or configuration                */
+    SLPIC_ENOMEM = -2,     /* workspace smaller than slpic_workspace_bytes */
+    SLPIC_ECAPACITY = -3,  /* particle buffer full (sticky device flag)   */
+    SLPIC_ENUMERIC = -4,   /* non-finite particle state (sticky flag)      */
+    SLPIC_EHIP = -5,       /* a HIP runtime call failed                    */
+    SLPIC_ESTATE = -6      /* call not valid in the context's state        */
+};
+
+/* Speed-limiting function: Eq. (11b) (default) or Eq. (11a). */
+enum { SLPIC_BETA_STEP = 0, SLPIC_BETA_SMOOTH = 1 };
+
+/* Particle precision.  Grids, deposits and the field solve are FP64 in both.
+ * SLPIC_F32: positions are int32 fixed-point grid coordinates, velocities
+ * FP32; SLPIC_F64: positions and velocities FP64. */
+enum { SLPIC_F32 = 0, SLPIC_F64 = 1 };
+
+/* Error flag bits reported in slpic_run_status.error_flags. */
+enum { SLPIC_FLAG_CAPACITY = 1, SLPIC_FLAG_NUMERIC = 2 };
+
+typedef struct {
+    double charge;       /* in units of e (electron: -1)           */
+    double mass;         /* in electron masses                       */
+    double temperature;  /* in T_e                                   */
+    int32_t ppc;         /* macroparticles per cell at load          */
+    int32_t reserved;
+} slpic_species;
+
+typedef struct {
+    int32_t nx;            /* cells (>= 4); nodes 0..nx                         */
+    int32_t beta_kind;     /* SLPIC_BETA_STEP / SLPIC_BETA_SMOOTH               */
+    double dx, dt;         /* cell size, time step                              */
+    double u;              /* speed limit v0; +INFINITY reduces to standard PIC */
+    int32_t nspecies;      /* must be 2: species 0 electrons, 1 ions            */
+    int32_t source_cells;  /* source region xt in [0, source_cells)            */
+    slpic_species species[2];
+    uint64_t seed;         /* Philox key                                         */
+    int32_t run_id;        /* enters the Philox counter                          */
+    int32_t reserved;
+    double capacity_factor;/* particle slots per species = ceil(cf * nx * ppc)  */
+} slpic_run_config;
+
+typedef struct {
+    int32_t precision;    /* SLPIC_F32 / SLPIC_F64 (all runs of a context)          */
+    int32_t sort_every;   /* stable cell sort + compaction every k steps; 0 = never  */
+    int32_t sort_bucket;  /* sort key = cell / bucket; 0 = compaction only (key 0)   */
+    int32_t chunk;        /* particles per push workgroup; 0 = default               */
+    int32_t block;        /* threads per push workgroup (64..1024); 0 = default      */
+    int32_t graph_steps;  /* steps captured per HIP graph; 0 = direct launches       */
+    int32_t sort_tile;    /* particles per sort workgroup; 0 = default               */
+    int32_t reserved;
+} slpic_tuning;
+
+typedef struct {
+    int64_t step;              /* completed steps                                  */
+    int64_t nslots[2];         /* occupied slots per species (live + dead holes)   */
+    int64_t capacity[2];
+    int64_t absorbed_total[2]; /* particles absorbed at the wall since load        */
+    int64_t injected_total[2]; /* particles injected by the source since load      */
+    double acc_e;              /* fractional electron injection carried over       */
+    double wall_potential;     /* phi(0) - phi(L) after the last field solve       */
+    int32_t error_flags;       /* SLPIC_FLAG_* bits (sticky)                       */
+    int32_t fixed_bits;        /* F32: fraction bits of the position fixed point   */
+    double weight[2];          /* macroparticle weight per species, dx Z / ppc     */
+} slpic_run_status;
+
+/* Bytes of device workspace needed for nruns runs (a sheath each) with the
+ * given tuning (NULL = defaults).  Returns 0 on an invalid configuration. */
+size_t slpic_workspace_bytes(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* tuning);
+
+/* Create a context over the caller's workspace and load every run cold:
+ * g0 = f0/beta (Eq. 5) sampled with Philox4x32-10 from each run's seed,
+ * weight dx Z/ppc with Z = <1/beta> over the Maxwellian; then (if sort_every
+ * > 0) the first cell sort, the beta-weighted deposit of rho^0 (Eq. A2c) and
+ * the field solve (Eq. A2d).  Async on stream; *out is valid on return. */
+int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* tuning,
+               void* d_workspace, size_t workspace_bytes, void* stream, void** out_ctx);
+
+/* Advance every run by nsteps leapfrog steps of Eq. (A2a-d): push and
+ * beta-weighted deposit, wall absorption, source injection, field solve,
+ * and the periodic cell sort.  Async (enqueue only; HIP-graph replays when
+ * tuning.graph_steps > 0). */
+int slpic_step(void* ctx, int32_t nsteps, void* stream);
+
+/* beta-weighted moments of the physical distribution f = beta g (Eq. 5) for
+ * one run at its current state, written to the caller's device buffer d_out
+ * of (1 + 3*2) * (nx+1) doubles, row-major: phi, then for species 0 and 1
+ * the density n, the flux Gamma_x = n <v_x> and the kinetic-energy density.
+ * Async on stream. */
+int slpic_moments(void* ctx, int32_t run, double* d_out, void* stream);
+
+/* Sync.  Copies the status of runs [0, nruns) to h_out. */
+int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns);
+
+/* Sync.  Copies the nslots occupied slots of (run, species) to host arrays
+ * of at least *n doubles: xt = x/dx (dead slots < 0), v_x and v_perp^2 =
+ * v_y^2 + v_z^2.  On entry *n is the host capacity; on return the count.
+ * Returns SLPIC_EINVAL if the arrays are too small. */
+int slpic_export_particles(void* ctx, int32_t run, int32_t species, double* h_xt, double* h_vx,
+                           double* h_vperp2, int64_t* n);
+
+/* Sync.  Replaces the particles of (run, species) with n slots from host
+ * arrays (layout as in export; F32 positions round to the fixed point).
+ * Fields are not recomputed: call slpic_refresh_fields(). */
+int slpic_import_particles(void* ctx, int32_t run, int32_t species, const double* h_xt,
+                           const double* h_vx, const double* h_vperp2, int64_t n);
+
+/* Sync.  Sets the step counter (enters the source's Philox counter) and the
+ * fractional electron-injection accumulator of one run. */
+int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e);
+
+/* Recompute rho (Eq. A2c, from the stored particles) and the fields
+ * (Eq. A2d) of every run without pushing.  Async. */
+int slpic_refresh_fields(void* ctx, void* stream);
+
+/* Sync.  Copies one run's last deposited charge per species (h_Q: 2*(nx+1)
+ * doubles, Q_j = sum q w beta W_j, so rho_j = Q_j/dV_j), potential and
+ * field at the nodes.  Any pointer may be NULL. */
+int slpic_export_grid(void* ctx, int32_t run, double* h_Q, double* h_phi, double* h_E);
+
+/* Run the stable cell sort (compaction) of every run now.  Async. */
+int slpic_sort_now(void* ctx, void* stream);
+
+/* Sync.  The permutation of the last sort of (run, species): h_perm[new] =
+ * old slot, *n entries (capacity on entry, count on return). */
+int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, int64_t* n);
+
+/* Kernel timing with HIP events on the launch stream (for roofline
+ * accounting).  enable != 0 switches slpic_step to direct launches with an
+ * event pair around every push-deposit, inject, field and sort launch and
+ * clears previous records.  slpic_profile_read (sync) returns the summed
+ * milliseconds and launch counts per kernel class in the order push, inject,
+ * field, sort (arrays of 4). */
+int slpic_profile(void* ctx, int32_t enable);
+int slpic_profile_read(void* ctx, double* h_ms, int64_t* h_launches);
+
+/* Live particles advanced by all push launches since slpic_init (summed
+ * over runs and species), for pushes/s accounting.  Sync. */
+int slpic_total_slots(void* ctx, int64_t* h_total);
+
+/* Release the context (not the caller's workspace).  Safe on NULL. */
+void slpic_destroy(void* ctx);
+
+/* Static description of an SLPIC_* code. */
+const char* slpic_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLPIC_H */

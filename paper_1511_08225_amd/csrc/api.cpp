@@ -1,0 +1,675 @@
+// api.cpp -- the C ABI of include/slpic.h: run planning (run table, work
+// tables, workspace layout), cold start, stepping with optional HIP-graph
+// replay, sort scheduling, state import/export and event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/slpic.h"
+#include "launch.h"
+#include "slpic_internal.h"
+
+using namespace slpic;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// <1/beta> over the Maxwell speed density sqrt(2/pi) s^2 exp(-s^2/2), speeds
+// in thermal units, ut = v0/vt.  Eq. (11b): closed form of the split at ut.
+// Eq. (11a): composite five-point Gauss-Legendre quadrature on [0, 40].
+void step_mixture(double ut, double& Ps, double& Pf) {
+    const double c = 0.7978845608028654;  // sqrt(2/pi)
+    double e = std::exp(-0.5 * ut * ut);
+    Ps = std::erf(ut / std::sqrt(2.0)) - c * ut * e;
+    Pf = c * (ut * ut + 2.0) * e / ut;
+}
+
+double mean_inv_beta(int kind, double ut) {
+    if (std::isinf(ut)) return 1.0;
+    if (kind == SLPIC_BETA_STEP) {
+        double Ps, Pf;
+        step_mixture(ut, Ps, Pf);
+        return Ps + Pf;
+    }
+    static const double xg[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831,
+                                 0.9061798459386640};
+    static const double wg[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
+                                 0.4786286704993665, 0.2369268850561891};
+    const int panels = 4000;
+    const double L = 40.0, h = L / panels;
+    double sum = 0.0;
+    for (int p = 0; p < panels; ++p) {
+        double mid = (p + 0.5) * h;
+        for (int k = 0; k < 5; ++k) {
+            double s = mid + 0.5 * h * xg[k];
+            double f = 0.7978845608028654 * s * s * std::exp(-0.5 * s * s) * std::sqrt(1.0 + (s / ut) * (s / ut));
+            sum += 0.5 * h * wg[k] * f;
+        }
+    }
+    return sum;
+}
+
+int ceil_log2(int64_t v) {
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+struct Layout {
+    size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, phi, Qacc, Qlast, hist,
+        totals, history, total;
+};
+
+struct Plan {
+    int nruns = 0;
+    slpic_tuning tun{};
+    std::vector<RunInfo> runs;
+    std::vector<Chunk> chunks;
+    std::vector<int> run_chunk0, run_nchunks;
+    std::vector<Tile> tiles;
+    int64_t total_slots = 0, total_nodes = 0, hist_entries = 0;
+    int max_nodes = 0, max_src = 0, max_nkeys = 0;
+    Layout L{};
+};
+
+int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, Plan& P) {
+    if (!cfg || nruns < 1) return SLPIC_EINVAL;
+    slpic_tuning t{};
+    if (tin) t = *tin;
+    if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
+    if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
+        t.sort_tile < 0)
+        return SLPIC_EINVAL;
+    if (t.chunk == 0) t.chunk = 4096;
+    if (t.block == 0) t.block = 256;
+    if (t.sort_tile == 0) t.sort_tile = 16384;
+    if (t.block < 64 || t.block > 1024 || t.block % 64) return SLPIC_EINVAL;
+    if (t.sort_every > 0 && t.graph_steps > 0 && t.graph_steps % t.sort_every)
+        t.graph_steps = (t.graph_steps / t.sort_every + 1) * t.sort_every;
+    P.tun = t;
+    P.nruns = nruns;
+    P.runs.assign(nruns, RunInfo{});
+    int64_t poff = 0, goff = 0, hoff = 0;
+    for (int r = 0; r < nruns; ++r) {
+        const slpic_run_config& c = cfg[r];
+        if (c.nx < 4 || c.nx > (1 << 20) || !(c.dx > 0) || !(c.dt > 0) || !(c.u > 0) || c.nspecies != 2 ||
+            c.source_cells < 1 || c.source_cells > c.nx ||
+            (c.beta_kind != SLPIC_BETA_STEP && c.beta_kind != SLPIC_BETA_SMOOTH))
+            return SLPIC_EINVAL;
+        RunInfo& R = P.runs[r];
+        R.nx = c.nx;
+        R.nodes = c.nx + 1;
+        R.beta_kind = c.beta_kind;
+        R.source_cells = c.source_cells;
+        R.fb = std::min(24, 31 - ceil_log2((int64_t)c.nx + 1));
+        R.bucket = t.sort_bucket;
+        R.nkeys = t.sort_bucket > 0 ? (c.nx + t.sort_bucket - 1) / t.sort_bucket : 1;
+        R.uinf = std::isinf(c.u) ? 1 : 0;
+        R.dx = c.dx;
+        R.dt = c.dt;
+        R.u = c.u;
+        R.u2 = c.u * c.u;
+        R.dtdx = c.dt / c.dx;
+        R.fscale = std::ldexp(1.0, R.fb);
+        R.inv_fscale = std::ldexp(1.0, -R.fb);
+        double cf = c.capacity_factor > 1.0 ? c.capacity_factor : 1.0;
+        for (int s = 0; s < 2; ++s) {
+            const slpic_species& sp = c.species[s];
+            if (!(sp.mass > 0) || !(sp.temperature > 0) || sp.ppc < 1) return SLPIC_EINVAL;
+            R.vt[s] = std::sqrt(sp.temperature / sp.mass);
+            R.mass[s] = sp.mass;
+            R.ut[s] = c.u / R.vt[s];
+            double Z = mean_inv_beta(c.beta_kind, R.ut[s]);
+            R.w[s] = c.dx * Z / (double)sp.ppc;
+            R.qw[s] = sp.charge * R.w[s];
+            R.qm[s] = sp.charge / sp.mass;
+            if (R.uinf) {
+                R.Ps[s] = 1.0;
+                R.Pf[s] = 0.0;
+            } else {
+                step_mixture(R.ut[s], R.Ps[s], R.Pf[s]);
+            }
+            R.nload[s] = (int64_t)c.nx * sp.ppc;
+            R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), R.nload[s] + 64);
+            if (R.cap[s] > (int64_t(1) << 31) - 1) return SLPIC_EINVAL;
+            R.poff[s] = poff;
+            poff += R.cap[s];
+            R.ntiles[s] = (int32_t)((R.cap[s] + t.sort_tile - 1) / t.sort_tile);
+            R.hoff[s] = hoff;
+            hoff += (int64_t)R.nkeys * R.ntiles[s];
+        }
+        R.inj_ratio = R.w[1] / R.w[0];
+        R.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
+        R.seed_hi = (uint32_t)(c.seed >> 32);
+        R.run_id = (uint32_t)c.run_id;
+        R.goff = goff;
+        goff += R.nodes;
+        P.max_nodes = std::max(P.max_nodes, R.nodes);
+        P.max_src = std::max(P.max_src, c.source_cells + 1);
+        P.max_nkeys = std::max(P.max_nkeys, R.nkeys);
+    }
+    P.total_slots = poff;
+    P.total_nodes = goff;
+    P.hist_entries = hoff;
+    P.run_chunk0.assign(nruns, 0);
+    P.run_nchunks.assign(nruns, 0);
+    for (int r = 0; r < nruns; ++r) {
+        P.run_chunk0[r] = (int)P.chunks.size();
+        for (int s = 0; s < 2; ++s) {
+            const RunInfo& R = P.runs[r];
+            for (int64_t b = 0; b < R.cap[s]; b += t.chunk)
+                P.chunks.push_back(Chunk{r, s, b, std::min<int64_t>(b + t.chunk, R.cap[s])});
+            for (int k = 0; k < R.ntiles[s]; ++k) {
+                int64_t b = (int64_t)k * t.sort_tile;
+                P.tiles.push_back(Tile{r, s, k, 0, b, std::min<int64_t>(b + t.sort_tile, R.cap[s])});
+            }
+        }
+        P.run_nchunks[r] = (int)P.chunks.size() - P.run_chunk0[r];
+    }
+    const size_t psz = t.precision == SLPIC_F32 ? 4 : 8;  // int32 fixed point or double
+    const size_t vsz = t.precision == SLPIC_F32 ? 4 : 8;
+    Layout& L = P.L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.runs = take(sizeof(RunInfo) * nruns);
+    L.state = take(sizeof(RunState) * nruns);
+    L.chunks = take(sizeof(Chunk) * P.chunks.size());
+    L.tiles = take(sizeof(Tile) * P.tiles.size());
+    L.cur = take(sizeof(int));
+    for (int b = 0; b < 2; ++b) {
+        L.x[b] = take(psz * P.total_slots);
+        L.vx[b] = take(vsz * P.total_slots);
+        L.vp2[b] = take(vsz * P.total_slots);
+    }
+    L.perm = take(sizeof(int32_t) * P.total_slots);
+    L.E = take(sizeof(double) * P.total_nodes);
+    L.phi = take(sizeof(double) * P.total_nodes);
+    L.Qacc = take(sizeof(double) * 2 * P.total_nodes);
+    L.Qlast = take(sizeof(double) * 2 * P.total_nodes);
+    L.hist = take(sizeof(int) * P.hist_entries);
+    L.totals = take(sizeof(int64_t) * 2 * nruns);
+    L.history = take(sizeof(double) * kHistoryLen * nruns);
+    L.total = o;
+    return SLPIC_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+struct Context {
+    Plan P;
+    KArgs a{};
+    unsigned char* ws = nullptr;
+    int64_t steps_done = 0;
+    size_t push_lds = 0, field_lds = 0, sort_lds = 0, inject_lds = 0, moments_lds = 0;
+    hipGraphExec_t gexec = nullptr;
+    int graph_len = 0;
+    bool prof = false;
+    std::vector<EventPair> ev[4];
+    size_t ev_used[4] = {0, 0, 0, 0};
+    ~Context() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        for (auto& v : ev)
+            for (auto& e : v) {
+                if (e.a) hipEventDestroy(e.a);
+                if (e.b) hipEventDestroy(e.b);
+            }
+    }
+};
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return SLPIC_EHIP;   \
+    } while (0)
+
+int prec(const Context* c) { return c->P.tun.precision; }
+
+void l_load(Context* c, hipStream_t s) {
+    if (prec(c) == SLPIC_F32) launch_load_f32(c->a, (int)c->P.chunks.size(), 256, s);
+    else launch_load_f64(c->a, (int)c->P.chunks.size(), 256, s);
+}
+void l_push(Context* c, bool push, hipStream_t s) {
+    if (prec(c) == SLPIC_F32) launch_push_f32(push, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
+    else launch_push_f64(push, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
+}
+void l_inject(Context* c, hipStream_t s) {
+    if (prec(c) == SLPIC_F32) launch_inject_f32(c->a, c->P.nruns, 256, c->inject_lds, s);
+    else launch_inject_f64(c->a, c->P.nruns, 256, c->inject_lds, s);
+}
+
+// timed launch wrapper: class k in {0 push, 1 inject, 2 field, 3 sort}
+template <typename F>
+int timed(Context* c, int k, hipStream_t s, F&& f) {
+    if (!c->prof) {
+        f();
+        return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+    }
+    if (c->ev_used[k] == c->ev[k].size()) {
+        EventPair e;
+        HIP_TRY(hipEventCreate(&e.a));
+        HIP_TRY(hipEventCreate(&e.b));
+        c->ev[k].push_back(e);
+    }
+    EventPair& e = c->ev[k][c->ev_used[k]++];
+    HIP_TRY(hipEventRecord(e.a, s));
+    f();
+    HIP_TRY(hipEventRecord(e.b, s));
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+}
+
+int do_sort(Context* c, hipStream_t s) {
+    const int nt = (int)c->P.tiles.size();
+    return timed(c, 3, s, [&] {
+        if (prec(c) == SLPIC_F32) launch_sort_hist_f32(c->a, nt, 256, c->sort_lds, s);
+        else launch_sort_hist_f64(c->a, nt, 256, c->sort_lds, s);
+        launch_sort_scan(c->a, c->P.nruns, s);
+        if (prec(c) == SLPIC_F32) launch_sort_scatter_f32(c->a, nt, 256, c->sort_lds, s);
+        else launch_sort_scatter_f64(c->a, nt, 256, c->sort_lds, s);
+        launch_sort_finish(c->a, c->P.nruns, s);
+    });
+}
+
+// One leapfrog step of every run; `local_step` decides the sort.
+int one_step(Context* c, int64_t local_step, hipStream_t s) {
+    int rc;
+    if ((rc = timed(c, 0, s, [&] { l_push(c, true, s); }))) return rc;
+    if ((rc = timed(c, 1, s, [&] { l_inject(c, s); }))) return rc;
+    if ((rc = timed(c, 2, s, [&] { launch_field(c->a, c->P.nruns, 1, c->field_lds, s); }))) return rc;
+    const int se = c->P.tun.sort_every;
+    if (se > 0 && (local_step + 1) % se == 0)
+        if ((rc = do_sort(c, s))) return rc;
+    return SLPIC_OK;
+}
+
+int build_graph(Context* c, hipStream_t s) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = SLPIC_OK;
+    for (int k = 0; k < c->P.tun.graph_steps && rc == SLPIC_OK; ++k) rc = one_step(c, k, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != SLPIC_OK || e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return rc != SLPIC_OK ? rc : SLPIC_EHIP;
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return SLPIC_EHIP;
+    }
+    c->graph_len = c->P.tun.graph_steps;
+    return SLPIC_OK;
+}
+
+Context* ctx_of(void* p) { return static_cast<Context*>(p); }
+
+int copy_d2h(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return SLPIC_OK;
+    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    return SLPIC_OK;
+}
+int copy_h2d(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return SLPIC_OK;
+    HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return SLPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t slpic_workspace_bytes(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* tuning) {
+    Plan P;
+    if (make_plan(runs, nruns, tuning, P) != SLPIC_OK) return 0;
+    return P.L.total;
+}
+
+int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* tuning, void* d_workspace,
+               size_t workspace_bytes, void* stream, void** out_ctx) {
+    if (!out_ctx) return SLPIC_EINVAL;
+    *out_ctx = nullptr;
+    Context* c = new (std::nothrow) Context();
+    if (!c) return SLPIC_ENOMEM;
+    int rc = make_plan(runs, nruns, tuning, c->P);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0) {
+        delete c;
+        return SLPIC_EINVAL;
+    }
+    if (workspace_bytes < c->P.L.total) {
+        delete c;
+        return SLPIC_ENOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char* w = (unsigned char*)d_workspace;
+    const Layout& L = c->P.L;
+    c->ws = w;
+    KArgs& a = c->a;
+    a.runs = (const RunInfo*)(w + L.runs);
+    a.state = (RunState*)(w + L.state);
+    a.chunks = (const Chunk*)(w + L.chunks);
+    a.tiles = (const Tile*)(w + L.tiles);
+    a.cur = (int*)(w + L.cur);
+    for (int b = 0; b < 2; ++b) {
+        a.bufs.x[b] = w + L.x[b];
+        a.bufs.vx[b] = w + L.vx[b];
+        a.bufs.vp2[b] = w + L.vp2[b];
+    }
+    a.perm = (int32_t*)(w + L.perm);
+    a.E = (double*)(w + L.E);
+    a.phi = (double*)(w + L.phi);
+    a.Qacc = (double*)(w + L.Qacc);
+    a.Qlast = (double*)(w + L.Qlast);
+    a.hist = (int*)(w + L.hist);
+    a.totals = (int64_t*)(w + L.totals);
+    a.history = (double*)(w + L.history);
+    const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
+    c->push_lds = (size_t)c->P.max_nodes * (8 + tsz) + 16;
+    c->field_lds = (size_t)c->P.max_nodes * 8 + 32 * 8;
+    c->sort_lds = (size_t)4 * c->P.max_nkeys * sizeof(int);
+    c->inject_lds = (size_t)2 * c->P.max_src * 8;
+    c->moments_lds = (size_t)3 * c->P.max_nodes * 8;
+    if (c->push_lds > 65536 || c->sort_lds > 65536 || c->moments_lds > 65536) {
+        delete c;
+        return SLPIC_EINVAL;
+    }
+#define INIT_TRY(x)              \
+    do {                         \
+        int r_ = (x);            \
+        if (r_) {                \
+            delete c;            \
+            return r_;           \
+        }                        \
+    } while (0)
+    INIT_TRY(hipMemcpyAsync((void*)a.runs, c->P.runs.data(), sizeof(RunInfo) * nruns, hipMemcpyHostToDevice, s)
+                 ? SLPIC_EHIP : SLPIC_OK);
+    INIT_TRY(hipMemcpyAsync((void*)a.chunks, c->P.chunks.data(), sizeof(Chunk) * c->P.chunks.size(),
+                            hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
+    INIT_TRY(hipMemcpyAsync((void*)a.tiles, c->P.tiles.data(), sizeof(Tile) * c->P.tiles.size(),
+                            hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
+    launch_init_state(a, nruns, s);
+    launch_zero(a.Qacc, 2 * c->P.total_nodes, s);
+    launch_zero(a.Qlast, 2 * c->P.total_nodes, s);
+    launch_zero(a.E, c->P.total_nodes, s);
+    launch_zero(a.phi, c->P.total_nodes, s);
+    launch_zero(a.history, (int64_t)kHistoryLen * nruns, s);
+    l_load(c, s);
+    if (c->P.tun.sort_every > 0) INIT_TRY(do_sort(c, s));
+    l_push(c, false, s);
+    launch_field(a, nruns, 0, c->field_lds, s);
+    INIT_TRY(hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP);
+    INIT_TRY(hipStreamSynchronize(s) == hipSuccess ? SLPIC_OK : SLPIC_EHIP);
+#undef INIT_TRY
+    *out_ctx = c;
+    return SLPIC_OK;
+}
+
+int slpic_step(void* ctx, int32_t nsteps, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c || nsteps < 0) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int se = c->P.tun.sort_every;
+    const bool graphs = c->P.tun.graph_steps > 0 && !c->prof && s != nullptr;
+    int32_t done = 0;
+    while (done < nsteps) {
+        const int gl = c->P.tun.graph_steps;
+        if (graphs && nsteps - done >= gl && (se == 0 || c->steps_done % se == 0)) {
+            if (!c->gexec) {
+                int rc = build_graph(c, s);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(c->gexec, s));
+            c->steps_done += gl;
+            done += gl;
+            continue;
+        }
+        int rc = one_step(c, c->steps_done, s);
+        if (rc) return rc;
+        c->steps_done += 1;
+        done += 1;
+    }
+    return SLPIC_OK;
+}
+
+int slpic_moments(void* ctx, int32_t run, double* d_out, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c || !d_out || run < 0 || run >= c->P.nruns) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const RunInfo& R = c->P.runs[run];
+    launch_zero(d_out, (int64_t)7 * R.nodes, s);
+    if (prec(c) == SLPIC_F32)
+        launch_moments_f32(c->a, c->P.run_chunk0[run], c->P.run_nchunks[run], 256, c->moments_lds, d_out, s);
+    else
+        launch_moments_f64(c->a, c->P.run_chunk0[run], c->P.run_nchunks[run], 256, c->moments_lds, d_out, s);
+    launch_moments_finish(c->a, run, d_out, s);
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+}
+
+int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns) {
+    Context* c = ctx_of(ctx);
+    if (!c || !h_out || nruns < 0 || nruns > c->P.nruns) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<RunState> st(nruns);
+    if (int rc = copy_d2h(st.data(), c->a.state, sizeof(RunState) * nruns)) return rc;
+    for (int r = 0; r < nruns; ++r) {
+        const RunInfo& R = c->P.runs[r];
+        slpic_run_status& o = h_out[r];
+        std::memset(&o, 0, sizeof o);
+        o.step = st[r].step;
+        for (int s = 0; s < 2; ++s) {
+            o.nslots[s] = st[r].nslots[s];
+            o.capacity[s] = R.cap[s];
+            o.absorbed_total[s] = st[r].absorbed_total[s];
+            o.injected_total[s] = st[r].injected_total[s];
+            o.weight[s] = R.w[s];
+        }
+        o.acc_e = st[r].acc_e;
+        o.wall_potential = st[r].phi_w;
+        o.error_flags = st[r].error;
+        o.fixed_bits = c->P.tun.precision == SLPIC_F32 ? R.fb : 0;
+    }
+    return SLPIC_OK;
+}
+
+static int cur_buffer(Context* c, int* b) {
+    HIP_TRY(hipDeviceSynchronize());
+    return copy_d2h(b, c->a.cur, sizeof(int));
+}
+
+int slpic_export_particles(void* ctx, int32_t run, int32_t species, double* h_xt, double* h_vx,
+                           double* h_vperp2, int64_t* n) {
+    Context* c = ctx_of(ctx);
+    if (!c || !n || run < 0 || run >= c->P.nruns || species < 0 || species > 1) return SLPIC_EINVAL;
+    int b = 0;
+    if (int rc = cur_buffer(c, &b)) return rc;
+    RunState st;
+    if (int rc = copy_d2h(&st, c->a.state + run, sizeof st)) return rc;
+    const int64_t cnt = st.nslots[species];
+    if (*n < cnt || (cnt && (!h_xt || !h_vx || !h_vperp2))) {
+        *n = cnt;
+        return SLPIC_EINVAL;
+    }
+    const RunInfo& R = c->P.runs[run];
+    const int64_t po = R.poff[species];
+    if (prec(c) == SLPIC_F32) {
+        std::vector<int32_t> x(cnt);
+        std::vector<float> vx(cnt), vp(cnt);
+        if (int rc = copy_d2h(x.data(), (int32_t*)c->a.bufs.x[b] + po, 4 * cnt)) return rc;
+        if (int rc = copy_d2h(vx.data(), (float*)c->a.bufs.vx[b] + po, 4 * cnt)) return rc;
+        if (int rc = copy_d2h(vp.data(), (float*)c->a.bufs.vp2[b] + po, 4 * cnt)) return rc;
+        for (int64_t i = 0; i < cnt; ++i) {
+            h_xt[i] = x[i] < 0 ? -1.0 : (double)x[i] * R.inv_fscale;
+            h_vx[i] = vx[i];
+            h_vperp2[i] = vp[i];
+        }
+    } else {
+        if (int rc = copy_d2h(h_xt, (double*)c->a.bufs.x[b] + po, 8 * cnt)) return rc;
+        if (int rc = copy_d2h(h_vx, (double*)c->a.bufs.vx[b] + po, 8 * cnt)) return rc;
+        if (int rc = copy_d2h(h_vperp2, (double*)c->a.bufs.vp2[b] + po, 8 * cnt)) return rc;
+    }
+    *n = cnt;
+    return SLPIC_OK;
+}
+
+int slpic_import_particles(void* ctx, int32_t run, int32_t species, const double* h_xt, const double* h_vx,
+                           const double* h_vperp2, int64_t n) {
+    Context* c = ctx_of(ctx);
+    if (!c || run < 0 || run >= c->P.nruns || species < 0 || species > 1 || n < 0) return SLPIC_EINVAL;
+    const RunInfo& R = c->P.runs[run];
+    if (n > R.cap[species] || (n && (!h_xt || !h_vx || !h_vperp2))) return SLPIC_EINVAL;
+    int b = 0;
+    if (int rc = cur_buffer(c, &b)) return rc;
+    const int64_t po = R.poff[species];
+    if (prec(c) == SLPIC_F32) {
+        std::vector<int32_t> x(n);
+        std::vector<float> vx(n), vp(n);
+        for (int64_t i = 0; i < n; ++i) {
+            double xt = h_xt[i];
+            if (!(xt >= 0.0)) x[i] = -1;
+            else if (!(xt < (double)R.nx)) return SLPIC_EINVAL;
+            else x[i] = (int32_t)std::llrint(xt * R.fscale);
+            if (x[i] >= (int32_t)((int64_t)R.nx << R.fb)) return SLPIC_EINVAL;
+            vx[i] = (float)h_vx[i];
+            vp[i] = (float)h_vperp2[i];
+        }
+        if (int rc = copy_h2d((int32_t*)c->a.bufs.x[b] + po, x.data(), 4 * n)) return rc;
+        if (int rc = copy_h2d((float*)c->a.bufs.vx[b] + po, vx.data(), 4 * n)) return rc;
+        if (int rc = copy_h2d((float*)c->a.bufs.vp2[b] + po, vp.data(), 4 * n)) return rc;
+    } else {
+        for (int64_t i = 0; i < n; ++i)
+            if (h_xt[i] >= (double)R.nx) return SLPIC_EINVAL;
+        if (int rc = copy_h2d((double*)c->a.bufs.x[b] + po, h_xt, 8 * n)) return rc;
+        if (int rc = copy_h2d((double*)c->a.bufs.vx[b] + po, h_vx, 8 * n)) return rc;
+        if (int rc = copy_h2d((double*)c->a.bufs.vp2[b] + po, h_vperp2, 8 * n)) return rc;
+    }
+    int64_t nn = n;
+    return copy_h2d(&c->a.state[run].nslots[species], &nn, sizeof nn);
+}
+
+int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e) {
+    Context* c = ctx_of(ctx);
+    if (!c || run < 0 || run >= c->P.nruns || step < 0) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    if (int rc = copy_h2d(&c->a.state[run].step, &step, sizeof step)) return rc;
+    if (int rc = copy_h2d(&c->a.state[run].acc_e, &acc_e, sizeof acc_e)) return rc;
+    c->steps_done = step;
+    return SLPIC_OK;
+}
+
+int slpic_refresh_fields(void* ctx, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    launch_zero(c->a.Qacc, 2 * c->P.total_nodes, s);
+    l_push(c, false, s);
+    launch_field(c->a, c->P.nruns, 0, c->field_lds, s);
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+}
+
+int slpic_export_grid(void* ctx, int32_t run, double* h_Q, double* h_phi, double* h_E) {
+    Context* c = ctx_of(ctx);
+    if (!c || run < 0 || run >= c->P.nruns) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    const RunInfo& R = c->P.runs[run];
+    if (h_Q)
+        if (int rc = copy_d2h(h_Q, c->a.Qlast + 2 * R.goff, sizeof(double) * 2 * R.nodes)) return rc;
+    if (h_phi)
+        if (int rc = copy_d2h(h_phi, c->a.phi + R.goff, sizeof(double) * R.nodes)) return rc;
+    if (h_E)
+        if (int rc = copy_d2h(h_E, c->a.E + R.goff, sizeof(double) * R.nodes)) return rc;
+    return SLPIC_OK;
+}
+
+int slpic_sort_now(void* ctx, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c) return SLPIC_EINVAL;
+    return do_sort(c, (hipStream_t)stream);
+}
+
+int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, int64_t* n) {
+    Context* c = ctx_of(ctx);
+    if (!c || !n || run < 0 || run >= c->P.nruns || species < 0 || species > 1) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    RunState st;
+    if (int rc = copy_d2h(&st, c->a.state + run, sizeof st)) return rc;
+    const int64_t cnt = st.nslots[species];
+    if (*n < cnt || (cnt && !h_perm)) {
+        *n = cnt;
+        return SLPIC_EINVAL;
+    }
+    const RunInfo& R = c->P.runs[run];
+    if (int rc = copy_d2h(h_perm, c->a.perm + R.poff[species], sizeof(int32_t) * cnt)) return rc;
+    *n = cnt;
+    return SLPIC_OK;
+}
+
+int slpic_profile(void* ctx, int32_t enable) {
+    Context* c = ctx_of(ctx);
+    if (!c) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    c->prof = enable != 0;
+    for (auto& u : c->ev_used) u = 0;
+    return SLPIC_OK;
+}
+
+int slpic_profile_read(void* ctx, double* h_ms, int64_t* h_launches) {
+    Context* c = ctx_of(ctx);
+    if (!c || !h_ms || !h_launches) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    for (int k = 0; k < 4; ++k) {
+        double sum = 0.0;
+        for (size_t i = 0; i < c->ev_used[k]; ++i) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, c->ev[k][i].a, c->ev[k][i].b));
+            sum += ms;
+        }
+        h_ms[k] = sum;
+        h_launches[k] = (int64_t)c->ev_used[k];
+    }
+    return SLPIC_OK;
+}
+
+int slpic_total_slots(void* ctx, int64_t* h_total) {
+    Context* c = ctx_of(ctx);
+    if (!c || !h_total) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<RunState> st(c->P.nruns);
+    if (int rc = copy_d2h(st.data(), c->a.state, sizeof(RunState) * c->P.nruns)) return rc;
+    int64_t t = 0;
+    for (auto& x : st) t += x.pushed_total;
+    *h_total = t;
+    return SLPIC_OK;
+}
+
+void slpic_destroy(void* ctx) { delete ctx_of(ctx); }
+
+const char* slpic_strerror(int code) {
+    switch (code) {
+        case SLPIC_OK: return "ok";
+        case SLPIC_EINVAL: return "invalid argument or configuration";
+        case SLPIC_ENOMEM: return "workspace too small";
+        case SLPIC_ECAPACITY: return "particle capacity exceeded";
+        case SLPIC_ENUMERIC: return "non-finite particle state";
+        case SLPIC_EHIP: return "HIP runtime error";
+        case SLPIC_ESTATE: return "call not valid in this state";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// launch.h -- host launchers of the library's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "slpic_internal.h"
+
+namespace slpic {
+
+#define SLPIC_DECLARE_LAUNCHERS(sfx)                                                                   \
+    void launch_load_##sfx(const KArgs& a, int nchunks, int block, hipStream_t s);                     \
+    void launch_push_##sfx(bool push, const KArgs& a, int nchunks, int block, size_t lds,              \
+                           hipStream_t s);                                                             \
+    void launch_inject_##sfx(const KArgs& a, int nruns, int block, size_t lds, hipStream_t s);         \
+    void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \
+                              double* out, hipStream_t s);                                             \
+    void launch_sort_hist_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);     \
+    void launch_sort_scatter_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);
+
+SLPIC_DECLARE_LAUNCHERS(f32)
+SLPIC_DECLARE_LAUNCHERS(f64)
+#undef SLPIC_DECLARE_LAUNCHERS
+
+// precision-independent kernels
+void launch_init_state(const KArgs& a, int nruns, hipStream_t s);
+void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s);
+void launch_sort_scan(const KArgs& a, int nruns, hipStream_t s);
+void launch_sort_finish(const KArgs& a, int nruns, hipStream_t s);
+void launch_zero(double* p, int64_t n, hipStream_t s);
+void launch_moments_finish(const KArgs& a, int run, double* out, hipStream_t s);
+
+}  // namespace slpic

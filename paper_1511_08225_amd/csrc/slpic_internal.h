@@ -1,0 +1,91 @@
+// slpic_internal.h -- device-side data layout shared by the library's HIP
+// translation units (run table, run state, work tables, kernel arguments).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slpic {
+
+constexpr int kMaxSpecies = 2;
+constexpr int kPurposeLoad = 1;
+constexpr int kPurposeInject = 2;
+constexpr int kHistoryLen = 4096;  // wall-potential ring per run
+
+// Immutable per-run parameters (device copy of the host plan).
+struct RunInfo {
+    int32_t nx, nodes, beta_kind, source_cells;
+    int32_t fb;           // F32: fraction bits of the fixed-point position
+    int32_t nkeys;        // sort keys (cells / bucket), at least 1
+    int32_t bucket;       // sort key = cell / bucket (0: key 0)
+    int32_t uinf;         // 1 if u == +inf (beta == 1)
+    double dx, dt, u, u2, dtdx;
+    double fscale, inv_fscale;  // 2^fb, 2^-fb
+    double qm[kMaxSpecies], qw[kMaxSpecies], w[kMaxSpecies];
+    double vt[kMaxSpecies], mass[kMaxSpecies];
+    double Ps[kMaxSpecies], Pf[kMaxSpecies], ut[kMaxSpecies];  // loader mixture of Eq. (11b)
+    double inj_ratio;     // w_ion / w_electron
+    uint32_t seed_lo, seed_hi, run_id, pad0;
+    int64_t cap[kMaxSpecies];    // slots per species
+    int64_t poff[kMaxSpecies];   // first slot in the global particle arrays
+    int64_t nload[kMaxSpecies];  // particles loaded cold
+    int64_t goff;                // first node in the global node arrays
+    int64_t hoff[kMaxSpecies];   // first entry of the sort histogram of (run, species)
+    int32_t ntiles[kMaxSpecies]; // sort tiles of (run, species)
+    int32_t pad1[2];
+};
+
+// Mutable per-run state, updated on the device.
+struct alignas(64) RunState {
+    int64_t nslots[kMaxSpecies];
+    int64_t absorbed_step[kMaxSpecies];
+    int64_t absorbed_total[kMaxSpecies];
+    int64_t injected_total[kMaxSpecies];
+    int64_t step;
+    int64_t pushed_total;        // live particles advanced by push launches
+    double acc_e;
+    double phi_w;
+    int32_t error;
+    int32_t pad;
+};
+
+// A contiguous slot range of one (run, species): one push / load / moments workgroup.
+struct Chunk {
+    int32_t run, species;
+    int64_t begin, end;
+};
+
+// Particle SoA buffers (double-buffered for the sort); positions are int32
+// fixed point (F32) or double (F64), velocities float or double.
+struct Bufs {
+    void* x[2];
+    void* vx[2];
+    void* vp2[2];
+};
+
+// A sort tile: contiguous slots of one (run, species), its index among the
+// tiles of that (run, species).
+struct Tile {
+    int32_t run, species, index, pad;
+    int64_t begin, end;
+};
+
+// Kernel arguments shared by every launch (device pointers into the workspace).
+struct KArgs {
+    const RunInfo* runs;
+    RunState* state;
+    const Chunk* chunks;
+    const Tile* tiles;
+    Bufs bufs;
+    int* cur;             // which of the two particle buffers is current
+    double* E;            // node field, per run at goff
+    double* phi;          // node potential
+    double* Qacc;         // deposit accumulators [run][species][nodes] at 2*goff
+    double* Qlast;        // last step's charge per species, same layout
+    double* history;      // wall-potential ring [run][kHistoryLen]
+    int* hist;            // sort histogram, per (run, species) at hoff
+    int64_t* totals;      // live slots after the sort [run][species]
+    int32_t* perm;        // last sort's permutation (new slot -> old slot)
+};
+
+}  // namespace slpic

@@ -1,0 +1,279 @@
+"""ctypes binding of libslpic.so (include/slpic.h).
+
+Argument marshalling only: every step of the SLPIC path runs in the HIP
+library.  PyTorch supplies the device workspace (a uint8 tensor) and the
+stream; nothing here computes the method.  Importing this module without the
+built library raises, so a missing extension can never fall back silently.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslpic.so")
+
+SLPIC_F32, SLPIC_F64 = 0, 1
+BETA_STEP, BETA_SMOOTH = 0, 1
+FLAG_CAPACITY, FLAG_NUMERIC = 1, 2
+PROFILE_CLASSES = ("push", "inject", "field", "sort")
+
+
+class SlpicError(RuntimeError):
+    pass
+
+
+class _Species(ctypes.Structure):
+    _fields_ = [("charge", ctypes.c_double), ("mass", ctypes.c_double),
+                ("temperature", ctypes.c_double), ("ppc", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RunConfig(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("beta_kind", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("u", ctypes.c_double),
+                ("nspecies", ctypes.c_int32), ("source_cells", ctypes.c_int32),
+                ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run_id", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("capacity_factor", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32),
+                ("sort_bucket", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("sort_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RunStatus(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("nslots", ctypes.c_int64 * 2),
+                ("capacity", ctypes.c_int64 * 2), ("absorbed_total", ctypes.c_int64 * 2),
+                ("injected_total", ctypes.c_int64 * 2), ("acc_e", ctypes.c_double),
+                ("wall_potential", ctypes.c_double), ("error_flags", ctypes.c_int32),
+                ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2)]
+
+    def as_dict(self) -> dict:
+        return {"step": self.step, "nslots": list(self.nslots), "capacity": list(self.capacity),
+                "absorbed_total": list(self.absorbed_total),
+                "injected_total": list(self.injected_total), "acc_e": self.acc_e,
+                "wall_potential": self.wall_potential, "error_flags": self.error_flags,
+                "fixed_bits": self.fixed_bits, "weight": list(self.weight)}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """Load libslpic.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SlpicError(f"{LIB_PATH} is missing: build it with paper_1511_08225_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "slpic_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(RunConfig), i32, ctypes.POINTER(Tuning)]),
+            "slpic_init": (ctypes.c_int, [ctypes.POINTER(RunConfig), i32, ctypes.POINTER(Tuning), _P,
+                                          ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+            "slpic_step": (ctypes.c_int, [_P, i32, _P]),
+            "slpic_moments": (ctypes.c_int, [_P, i32, _P, _P]),
+            "slpic_status_query": (ctypes.c_int, [_P, ctypes.POINTER(RunStatus), i32]),
+            "slpic_export_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, _PI64]),
+            "slpic_import_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, i64]),
+            "slpic_set_counters": (ctypes.c_int, [_P, i32, i64, ctypes.c_double]),
+            "slpic_refresh_fields": (ctypes.c_int, [_P, _P]),
+            "slpic_export_grid": (ctypes.c_int, [_P, i32, _PD, _PD, _PD]),
+            "slpic_sort_now": (ctypes.c_int, [_P, _P]),
+            "slpic_export_perm": (ctypes.c_int, [_P, i32, i32, _PI32, _PI64]),
+            "slpic_profile": (ctypes.c_int, [_P, i32]),
+            "slpic_profile_read": (ctypes.c_int, [_P, _PD, _PI64]),
+            "slpic_total_slots": (ctypes.c_int, [_P, _PI64]),
+            "slpic_destroy": (None, [_P]),
+            "slpic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SlpicError(f"{what}: {lib().slpic_strerror(rc).decode()} ({rc})")
+
+
+def _beta_kind(v) -> int:
+    if isinstance(v, str):
+        return {"step": BETA_STEP, "smooth": BETA_SMOOTH}[v]
+    return int(v)
+
+
+def run_config(cfg: dict) -> RunConfig:
+    """Marshal a sheath description (nx, dx, dt, u, beta_kind, species,
+    source_cells, seed, run, capacity_factor) into the C struct."""
+    c = RunConfig()
+    c.nx = int(cfg["nx"])
+    c.beta_kind = _beta_kind(cfg.get("beta_kind", "step"))
+    c.dx, c.dt, c.u = float(cfg["dx"]), float(cfg["dt"]), float(cfg["u"])
+    sp = cfg["species"]
+    c.nspecies = len(sp)
+    for k, s in enumerate(sp):
+        c.species[k].charge = float(s["charge"])
+        c.species[k].mass = float(s["mass"])
+        c.species[k].temperature = float(s["temperature"])
+        c.species[k].ppc = int(s["ppc"])
+    c.source_cells = int(cfg.get("source_cells", 4))
+    c.seed = int(cfg.get("seed", 0))
+    c.run_id = int(cfg.get("run", 0))
+    c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
+    return c
+
+
+def tuning(precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0, graph_steps=0,
+           sort_tile=0) -> Tuning:
+    t = Tuning()
+    t.precision = {"f32": SLPIC_F32, "f64": SLPIC_F64}[precision] if isinstance(precision, str) else int(precision)
+    t.sort_every, t.sort_bucket, t.chunk, t.block = int(sort_every), int(sort_bucket), int(chunk), int(block)
+    t.graph_steps, t.sort_tile = int(graph_steps), int(sort_tile)
+    return t
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_PD)
+
+
+class Sim:
+    """One or more independent 1D3V sheaths advanced together on one GPU."""
+
+    def __init__(self, configs, precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0,
+                 graph_steps=0, sort_tile=0, device="cuda"):
+        if isinstance(configs, dict):
+            configs = [configs]
+        self.configs = [dict(c) for c in configs]
+        self.nruns = len(self.configs)
+        self.precision = precision
+        self._cfg = (RunConfig * self.nruns)(*[run_config(c) for c in self.configs])
+        self._tun = tuning(precision, sort_every, sort_bucket, chunk, block, graph_steps, sort_tile)
+        L = lib()
+        nbytes = L.slpic_workspace_bytes(self._cfg, self.nruns, ctypes.byref(self._tun))
+        if nbytes == 0:
+            raise SlpicError("invalid configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.workspace_bytes = nbytes
+        self._ctx = _P()
+        _check(L.slpic_init(self._cfg, self.nruns, ctypes.byref(self._tun), _P(self._ws_ptr), nbytes,
+                            self._stream(), ctypes.byref(self._ctx)), "slpic_init")
+
+    def _stream(self):
+        return _P(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            torch.cuda.synchronize(self.device)
+            lib().slpic_destroy(self._ctx)
+            self._ctx = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- stepping
+    def step(self, n: int = 1):
+        _check(lib().slpic_step(self._ctx, int(n), self._stream()), "slpic_step")
+
+    def refresh_fields(self):
+        _check(lib().slpic_refresh_fields(self._ctx, self._stream()), "slpic_refresh_fields")
+
+    def sort_now(self):
+        _check(lib().slpic_sort_now(self._ctx, self._stream()), "slpic_sort_now")
+
+    # ---------------------------------------------------------------- state
+    def status(self, run: int | None = None):
+        st = (RunStatus * self.nruns)()
+        _check(lib().slpic_status_query(self._ctx, st, self.nruns), "slpic_status_query")
+        out = [s.as_dict() for s in st]
+        return out if run is None else out[run]
+
+    def export_particles(self, run: int, species: int):
+        n = ctypes.c_int64(0)
+        lib().slpic_export_particles(self._ctx, run, species, None, None, None, ctypes.byref(n))
+        cnt = n.value
+        x, vx, vp = (np.zeros(max(cnt, 1)) for _ in range(3))
+        n = ctypes.c_int64(max(cnt, 1))
+        _check(lib().slpic_export_particles(self._ctx, run, species, _dp(x), _dp(vx), _dp(vp),
+                                            ctypes.byref(n)), "slpic_export_particles")
+        k = n.value
+        return x[:k], vx[:k], vp[:k]
+
+    def import_particles(self, run: int, species: int, xt, vx, vperp2):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (xt, vx, vperp2)]
+        _check(lib().slpic_import_particles(self._ctx, run, species, *[_dp(a) for a in arrs],
+                                            len(arrs[0])), "slpic_import_particles")
+
+    def set_counters(self, run: int, step: int, acc_e: float):
+        _check(lib().slpic_set_counters(self._ctx, run, int(step), float(acc_e)), "slpic_set_counters")
+
+    def grid(self, run: int = 0):
+        nodes = self.configs[run]["nx"] + 1
+        Q = np.zeros(2 * nodes)
+        phi = np.zeros(nodes)
+        E = np.zeros(nodes)
+        _check(lib().slpic_export_grid(self._ctx, run, _dp(Q), _dp(phi), _dp(E)), "slpic_export_grid")
+        return {"Q": Q.reshape(2, nodes), "phi": phi, "E": E}
+
+    def perm(self, run: int, species: int) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        lib().slpic_export_perm(self._ctx, run, species, None, ctypes.byref(n))
+        p = np.zeros(max(n.value, 1), dtype=np.int32)
+        n = ctypes.c_int64(len(p))
+        _check(lib().slpic_export_perm(self._ctx, run, species, p.ctypes.data_as(_PI32),
+                                       ctypes.byref(n)), "slpic_export_perm")
+        return p[: n.value]
+
+    def moments(self, run: int = 0) -> torch.Tensor:
+        nodes = self.configs[run]["nx"] + 1
+        out = torch.empty((7, nodes), dtype=torch.float64, device=self.device)
+        _check(lib().slpic_moments(self._ctx, run, _P(out.data_ptr()), self._stream()), "slpic_moments")
+        return out
+
+    def wall_potential(self, run: int = 0) -> float:
+        return self.status(run)["wall_potential"]
+
+    # ---------------------------------------------------------------- timing
+    def profile(self, enable: bool = True):
+        _check(lib().slpic_profile(self._ctx, 1 if enable else 0), "slpic_profile")
+
+    def profile_read(self) -> dict:
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        _check(lib().slpic_profile_read(self._ctx, ms, n), "slpic_profile_read")
+        return {k: {"ms": ms[i], "launches": n[i]} for i, k in enumerate(PROFILE_CLASSES)}
+
+    def pushed_total(self) -> int:
+        """Live particles advanced by push launches since init (all runs)."""
+        t = ctypes.c_int64(0)
+        _check(lib().slpic_total_slots(self._ctx, ctypes.byref(t)), "slpic_total_slots")
+        return t.value
+
+
+def fixed_point_round(xt: np.ndarray, fixed_bits: int) -> np.ndarray:
+    """Positions as an F32 context stores them: round-to-nearest-even on the
+    2^-fixed_bits grid (dead slots, xt < 0, stay negative)."""
+    xt = np.asarray(xt, dtype=np.float64)
+    scale = math.ldexp(1.0, fixed_bits)
+    q = np.rint(xt * scale) / scale
+    return np.where(xt < 0, -1.0, q)

@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every symbol include/slpic.h declares
+(no compute calls: this runs without a GPU), and the host-side planning
+validates configurations."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(slpic_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    import torch  # noqa: F401  (the library shares torch's HIP runtime)
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_planning_validates_configs():
+    import torch  # noqa: F401
+    import workloads
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    good = slpic.run_config(workloads.small_sheath())
+    t = slpic.tuning("f64")
+    n = L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(t))
+    assert n > 0
+    # more particles need more bytes; F64 more than F32
+    big = slpic.run_config(workloads.small_sheath(ppc=200))
+    assert L.slpic_workspace_bytes(ctypes.byref(big), 1, ctypes.byref(t)) > n
+    t32 = slpic.tuning("f32")
+    assert L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(t32)) < n
+    for bad in ({"nx": 2}, {"dx": 0.0}, {"dt": -1.0}, {"source_cells": 0}, {"u": 0.0},
+                {"beta_kind": 7}):
+        cfg = workloads.small_sheath()
+        cfg.update(bad)
+        c = slpic.run_config(cfg)
+        assert L.slpic_workspace_bytes(ctypes.byref(c), 1, ctypes.byref(t)) == 0, bad
+    assert L.slpic_workspace_bytes(ctypes.byref(good), 0, ctypes.byref(t)) == 0
+    tb = slpic.tuning("f32", block=100)
+    assert L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(tb)) == 0
+    inf = slpic.run_config(workloads.sheath(nx=64, ppc=10, u_over_vti=math.inf))
+    assert L.slpic_workspace_bytes(ctypes.byref(inf), 1, ctypes.byref(t)) > 0
+
+
+def test_strerror():
+    import torch  # noqa: F401
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    assert L.slpic_strerror(0) == b"ok"
+    assert b"workspace" in L.slpic_strerror(-2)
+    assert L.slpic_strerror(12345) == b"unknown error"
+
+
+def test_init_rejects_bad_workspace_without_touching_gpu():
+    import torch  # noqa: F401
+    import workloads
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    c = slpic.run_config(workloads.small_sheath())
+    t = slpic.tuning("f64")
+    ctx = ctypes.c_void_p()
+    # misaligned workspace pointer and a too-small workspace are refused before any HIP call
+    rc = L.slpic_init(ctypes.byref(c), 1, ctypes.byref(t), ctypes.c_void_p(8), 1 << 30, None,
+                      ctypes.byref(ctx))
+    assert rc == -1 and not ctx.value
+    rc = L.slpic_init(ctypes.byref(c), 1, ctypes.byref(t), ctypes.c_void_p(1 << 20), 16, None,
+                      ctypes.byref(ctx))
+    assert rc == -2 and not ctx.value
