@@ -188,6 +188,18 @@ int slpic_profile_read(void* ctx, double* h_ms, int64_t* h_launches);
  * over runs and species), for pushes/s accounting.  Sync. */
 int slpic_total_slots(void* ctx, int64_t* h_total);
 
+/* The velocity update of Eq. (A2a) alone, on caller device arrays of n
+ * particles (float when precision = SLPIC_F32, double otherwise): d_out[i]
+ * = v_x^{n+1/2} from d_vx[i] = v_x^{n-1/2}, d_vperp2[i] = v_y^2 + v_z^2 and
+ * the acceleration d_a[i] = (q/m) E_x held fixed over the step, with the
+ * integral of beta along the velocity path taken exactly (Eq. 11a or 11b
+ * by beta_kind; u = +INFINITY gives v + a dt).  d_iters (nullable, int32)
+ * receives the Newton iterations each particle used.  Async on stream;
+ * SLPIC_EINVAL on bad arguments. */
+int slpic_velocity_map(int32_t precision, int32_t beta_kind, double u, double dt, int64_t n,
+                       const void* d_vx, const void* d_vperp2, const void* d_a, void* d_out,
+                       int32_t* d_iters, void* stream);
+
 /* Release the context (not the caller's workspace).  Safe on NULL. */
 void slpic_destroy(void* ctx);
 

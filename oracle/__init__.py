@@ -234,8 +234,11 @@ class Run:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_destroy(h)
+        if h and _lib is not None:
+            try:
+                _lib.orc_destroy(h)
+            except Exception:  # interpreter teardown
+                pass
             self._h = None
 
     # state ------------------------------------------------------------

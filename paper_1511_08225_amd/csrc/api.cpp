@@ -11,7 +11,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/slpic.h"
+#include "slpic.h"
 #include "launch.h"
 #include "slpic_internal.h"
 
@@ -65,7 +65,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, phi, Qacc, Qlast, hist,
-        totals, history, total;
+        totals, btot, history, total;
 };
 
 struct Plan {
@@ -88,10 +88,14 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
         t.sort_tile < 0)
         return SLPIC_EINVAL;
-    if (t.chunk == 0) t.chunk = 4096;
     if (t.block == 0) t.block = 256;
+    if (t.chunk == 0) t.chunk = t.block * (t.precision == SLPIC_F32 ? 8 : 4);
     if (t.sort_tile == 0) t.sort_tile = 16384;
     if (t.block < 64 || t.block > 1024 || t.block % 64) return SLPIC_EINVAL;
+    {   // particles per thread in the push: chunk = block * P, P in {1, 2, 4, 8}
+        const int per = t.chunk / t.block;
+        if (t.chunk % t.block || (per != 1 && per != 2 && per != 4 && per != 8)) return SLPIC_EINVAL;
+    }
     if (t.sort_every > 0 && t.graph_steps > 0 && t.graph_steps % t.sort_every)
         t.graph_steps = (t.graph_steps / t.sort_every + 1) * t.sort_every;
     P.tun = t;
@@ -156,6 +160,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         P.max_src = std::max(P.max_src, c.source_cells + 1);
         P.max_nkeys = std::max(P.max_nkeys, R.nkeys);
     }
+    if (poff > (int64_t(1) << 31) - 1) return SLPIC_EINVAL;  // sort offsets are int32
     P.total_slots = poff;
     P.total_nodes = goff;
     P.hist_entries = hoff;
@@ -200,6 +205,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.Qlast = take(sizeof(double) * 2 * P.total_nodes);
     L.hist = take(sizeof(int) * P.hist_entries);
     L.totals = take(sizeof(int64_t) * 2 * nruns);
+    L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
     L.total = o;
     return SLPIC_OK;
@@ -213,6 +219,7 @@ struct Context {
     Plan P;
     KArgs a{};
     unsigned char* ws = nullptr;
+    long long* btot = nullptr;
     int64_t steps_done = 0;
     size_t push_lds = 0, field_lds = 0, sort_lds = 0, inject_lds = 0, moments_lds = 0;
     hipGraphExec_t gexec = nullptr;
@@ -242,8 +249,11 @@ void l_load(Context* c, hipStream_t s) {
     else launch_load_f64(c->a, (int)c->P.chunks.size(), 256, s);
 }
 void l_push(Context* c, bool push, hipStream_t s) {
-    if (prec(c) == SLPIC_F32) launch_push_f32(push, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
-    else launch_push_f64(push, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
+    const int per = c->P.tun.chunk / c->P.tun.block;
+    if (prec(c) == SLPIC_F32)
+        launch_push_f32(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
+    else
+        launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
 }
 void l_inject(Context* c, hipStream_t s) {
     if (prec(c) == SLPIC_F32) launch_inject_f32(c->a, c->P.nruns, 256, c->inject_lds, s);
@@ -275,10 +285,10 @@ int do_sort(Context* c, hipStream_t s) {
     return timed(c, 3, s, [&] {
         if (prec(c) == SLPIC_F32) launch_sort_hist_f32(c->a, nt, 256, c->sort_lds, s);
         else launch_sort_hist_f64(c->a, nt, 256, c->sort_lds, s);
-        launch_sort_scan(c->a, c->P.nruns, s);
+        launch_sort_scan(c->a, c->P.hist_entries, c->btot, s);
         if (prec(c) == SLPIC_F32) launch_sort_scatter_f32(c->a, nt, 256, c->sort_lds, s);
         else launch_sort_scatter_f64(c->a, nt, 256, c->sort_lds, s);
-        launch_sort_finish(c->a, c->P.nruns, s);
+        launch_sort_finish(c->a, c->P.nruns, c->P.hist_entries, c->btot, s);
     });
 }
 
@@ -379,6 +389,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.hist = (int*)(w + L.hist);
     a.totals = (int64_t*)(w + L.totals);
     a.history = (double*)(w + L.history);
+    c->btot = (long long*)(w + L.btot);
     const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
     c->push_lds = (size_t)c->P.max_nodes * (8 + tsz) + 16;
     c->field_lds = (size_t)c->P.max_nodes * 8 + 32 * 8;
@@ -655,6 +666,21 @@ int slpic_total_slots(void* ctx, int64_t* h_total) {
     for (auto& x : st) t += x.pushed_total;
     *h_total = t;
     return SLPIC_OK;
+}
+
+int slpic_velocity_map(int32_t precision, int32_t beta_kind, double u, double dt, int64_t n, const void* d_vx,
+                       const void* d_vperp2, const void* d_a, void* d_out, int32_t* d_iters, void* stream) {
+    if (n < 0 || (n > 0 && (!d_vx || !d_vperp2 || !d_a || !d_out)) || !(u > 0) || !(dt > 0) ||
+        (beta_kind != SLPIC_BETA_STEP && beta_kind != SLPIC_BETA_SMOOTH))
+        return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == SLPIC_F32)
+        launch_velocity_map_f32(beta_kind, u, dt, n, d_vx, d_vperp2, d_a, d_out, d_iters, s);
+    else if (precision == SLPIC_F64)
+        launch_velocity_map_f64(beta_kind, u, dt, n, d_vx, d_vperp2, d_a, d_out, d_iters, s);
+    else
+        return SLPIC_EINVAL;
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
 }
 
 void slpic_destroy(void* ctx) { delete ctx_of(ctx); }

@@ -138,34 +138,67 @@ __global__ void k_field(KArgs a, int advance) {
     }
 }
 
-// Exclusive scan of the key-major sort histogram of one (run, species), in
-// place; the total is the live count after the sort.
-__global__ void k_sort_scan(KArgs a) {
-    const int run = blockIdx.x >> 1, s = blockIdx.x & 1;
-    const RunInfo& R = a.runs[run];
-    int* h = a.hist + R.hoff[s];
-    const int64_t n = (int64_t)R.nkeys * R.ntiles[s];
+// Exclusive scan of the sort histogram, in place, over all (run, species)
+// segments at once: block sums, a scan of the block sums, then each block
+// rescanned with its offset.  A segment's first entry is then its base and
+// the next segment's first entry (or the grand total) its end.
+constexpr int kScanBlock = 8192;
+
+__global__ void k_scan_blocks(int* h, int64_t n, long long* btot) {
     __shared__ long long tmp[17];
-    const int64_t per = (n + blockDim.x - 1) / blockDim.x;
-    const int64_t j0 = (int64_t)threadIdx.x * per, j1 = min(j0 + per, n);
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    const int64_t b1 = min(b0 + kScanBlock, n);
+    long long loc = 0;
+    for (int64_t j = b0 + threadIdx.x; j < b1; j += blockDim.x) loc += h[j];
+    // block total via the scan helper
+    long long ex = block_scan<long long>(loc, tmp, false);
+    if (threadIdx.x == blockDim.x - 1) btot[blockIdx.x] = ex + loc;
+}
+
+__global__ void k_scan_top(long long* btot, int nblk) {
+    __shared__ long long tmp[17];
+    const int per = (nblk + blockDim.x - 1) / blockDim.x;
+    const int j0 = threadIdx.x * per, j1 = min(j0 + per, nblk);
+    long long loc = 0;
+    for (int j = j0; j < j1; ++j) loc += btot[j];
+    long long run = block_scan<long long>(loc, tmp, false);
+    for (int j = j0; j < j1; ++j) {
+        long long c = btot[j];
+        btot[j] = run;
+        run += c;
+    }
+    if (threadIdx.x == blockDim.x - 1) btot[nblk] = run;  // grand total
+}
+
+__global__ void k_scan_apply(int* h, int64_t n, const long long* btot) {
+    __shared__ long long tmp[17];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    const int64_t b1 = min(b0 + kScanBlock, n);
+    const int per = (kScanBlock + blockDim.x - 1) / blockDim.x;
+    const int64_t j0 = b0 + (int64_t)threadIdx.x * per, j1 = min(j0 + per, b1);
     long long loc = 0;
     for (int64_t j = j0; j < j1; ++j) loc += h[j];
-    long long run_s = block_scan<long long>(loc, tmp, false);
+    long long run = btot[blockIdx.x] + block_scan<long long>(loc, tmp, false);
     for (int64_t j = j0; j < j1; ++j) {
         long long c = h[j];
-        h[j] = (int)run_s;
-        run_s += c;
+        h[j] = (int)run;
+        run += c;
     }
-    if (threadIdx.x == blockDim.x - 1) a.totals[2 * run + s] = run_s;
 }
 
 // After the scatter: the sorted buffer becomes current and holds exactly the
-// live particles.
-__global__ void k_sort_finish(KArgs a, int nruns) {
+// live particles of each (run, species).
+__global__ void k_sort_finish(KArgs a, int nruns, int64_t hist_entries, const long long* btot, int nblk) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r == 0) *a.cur ^= 1;
     if (r >= nruns) return;
-    for (int s = 0; s < kMaxSpecies; ++s) a.state[r].nslots[s] = a.totals[2 * r + s];
+    const RunInfo& R = a.runs[r];
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        const int64_t e = R.hoff[s] + (int64_t)R.nkeys * R.ntiles[s];
+        const long long base = a.hist[R.hoff[s]];
+        const long long end = e < hist_entries ? (long long)a.hist[e] : btot[nblk];
+        a.state[r].nslots[s] = end - base;
+    }
 }
 
 __global__ void k_zero(double* p, int64_t n) {
@@ -191,11 +224,17 @@ void launch_init_state(const KArgs& a, int nruns, hipStream_t s) {
 void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL(k_field, dim3(nruns), dim3(1024), lds, s, a, advance);
 }
-void launch_sort_scan(const KArgs& a, int nruns, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_scan, dim3(2 * nruns), dim3(1024), 0, s, a);
+int scan_blocks(int64_t n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
+void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s) {
+    const int nblk = scan_blocks(hist_entries);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(1024), 0, s, a.hist, hist_entries, btot);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, btot, nblk);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(1024), 0, s, a.hist, hist_entries, (const long long*)btot);
 }
-void launch_sort_finish(const KArgs& a, int nruns, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_finish, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns);
+void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const long long* btot,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_finish, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns, hist_entries,
+                       btot, scan_blocks(hist_entries));
 }
 void launch_zero(double* p, int64_t n, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;

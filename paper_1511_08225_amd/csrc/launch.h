@@ -9,8 +9,11 @@ namespace slpic {
 
 #define SLPIC_DECLARE_LAUNCHERS(sfx)                                                                   \
     void launch_load_##sfx(const KArgs& a, int nchunks, int block, hipStream_t s);                     \
-    void launch_push_##sfx(bool push, const KArgs& a, int nchunks, int block, size_t lds,              \
-                           hipStream_t s);                                                             \
+    void launch_push_##sfx(bool push, int per_thread, const KArgs& a, int nchunks, int block,          \
+                           size_t lds, hipStream_t s);                                                 \
+    void launch_velocity_map_##sfx(int beta_kind, double u, double dt, int64_t n, const void* vx,      \
+                                   const void* c2, const void* acc, void* out, int* iters,             \
+                                   hipStream_t s);                                                     \
     void launch_inject_##sfx(const KArgs& a, int nruns, int block, size_t lds, hipStream_t s);         \
     void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \
                               double* out, hipStream_t s);                                             \
@@ -24,8 +27,10 @@ SLPIC_DECLARE_LAUNCHERS(f64)
 // precision-independent kernels
 void launch_init_state(const KArgs& a, int nruns, hipStream_t s);
 void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s);
-void launch_sort_scan(const KArgs& a, int nruns, hipStream_t s);
-void launch_sort_finish(const KArgs& a, int nruns, hipStream_t s);
+int scan_blocks(int64_t hist_entries);
+void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s);
+void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const long long* btot,
+                        hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);
 void launch_moments_finish(const KArgs& a, int run, double* out, hipStream_t s);
 

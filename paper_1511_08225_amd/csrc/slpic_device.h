@@ -71,6 +71,34 @@ struct Stream {
 };
 
 // ---------------------------------------------------------------------------
+// Elementary functions of the particle arithmetic.  Float uses the gfx950
+// hardware instructions (v_sqrt/v_rcp/v_rsq/v_log_f32, ~1 ulp), which the
+// float tolerances absorb; double keeps the correctly rounded library forms.
+// ---------------------------------------------------------------------------
+template <typename T> struct Fm;
+template <> struct Fm<float> {
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+    // log(1 + y) for small y: log(w) * y / (w - 1) with w = 1 + y keeps the
+    // relative accuracy of y (the rounding of w cancels).
+    static __device__ __forceinline__ float log1p(float y) {
+        const float w = 1.0f + y;
+        return (w == 1.0f) ? y : log(w) * div(y, w - 1.0f);
+    }
+};
+template <> struct Fm<double> {
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double log(double x) { return ::log(x); }
+    static __device__ __forceinline__ double log1p(double y) { return ::log1p(y); }
+};
+
+// ---------------------------------------------------------------------------
 // Speed-limiting functions of the squared speed.
 // ---------------------------------------------------------------------------
 enum { kBetaStep = 0, kBetaSmooth = 1 };
@@ -78,8 +106,31 @@ enum { kBetaStep = 0, kBetaSmooth = 1 };
 template <int BK, typename T>
 __device__ __forceinline__ T beta_s2(T s2, T u, T u2, bool uinf) {
     if (uinf) return T(1);
-    if (BK == kBetaSmooth) return T(1) / sqrt(T(1) + s2 / u2);  // Eq. (11a)
-    return (s2 <= u2) ? T(1) : u / sqrt(s2);                    // Eq. (11b), beta(v0) = 1
+    if (sizeof(T) == 8) {  // double: the correctly rounded forms
+        if (BK == kBetaSmooth) return T(1) / sqrt(T(1) + s2 / u2);  // Eq. (11a)
+        return (s2 <= u2) ? T(1) : u / sqrt(s2);                    // Eq. (11b), beta(v0) = 1
+    }
+    if (BK == kBetaSmooth) return Fm<T>::rsqrt(T(1) + Fm<T>::div(s2, u2));
+    return (s2 <= u2) ? T(1) : u * Fm<T>::rsqrt(s2);
+}
+
+// beta of Eq. (11a)/(11b) in FP64 from the stored particle velocity, for the
+// charge deposit.  Float particles: the quasi-neutral net charge is ~1e-3 of
+// either species' charge, so float rounding of the deposit weight would be
+// amplified ~1e3 in E; the weight is taken in double instead (hardware
+// reciprocal square root plus one Newton step, ~1e-13).  Double particles
+// use the correctly rounded form.
+template <int BK, typename T>
+__device__ __forceinline__ double beta_deposit(T vx, T c2, double u, double u2, bool uinf) {
+    if (uinf) return 1.0;
+    const double v = (double)vx;
+    const double s2 = v * v + (double)c2;
+    if (BK == kBetaSmooth) return 1.0 / sqrt(1.0 + s2 / u2);
+    if (s2 <= u2) return 1.0;
+    if (sizeof(T) == 8) return u / sqrt(s2);
+    double y = __builtin_amdgcn_rsq(s2);
+    y = y * (1.5 - 0.5 * s2 * y * y);
+    return u * y;
 }
 
 template <typename T> struct Eps;
@@ -92,67 +143,91 @@ template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-
 template <typename T>
 __device__ __forceinline__ T G_of(T c2, T c, T p, T s) {
     if (c2 == T(0)) return T(0.5) * p * fabs(p);
-    T ap = fabs(p);
-    T r = ap / c;
-    T ash;
+    const T ap = fabs(p);
+    const T r = Fm<T>::div(ap, c);
+    T ash;  // asinh(|p|/c)
     if (r < T(0.5)) {
-        T q = sqrt(T(1) + r * r);
-        ash = log1p(r + r * r / (T(1) + q));
+        const T q = Fm<T>::sqrt(T(1) + r * r);
+        ash = Fm<T>::log1p(r + Fm<T>::div(r * r, T(1) + q));
     } else {
-        ash = log((ap + s) / c);
+        ash = Fm<T>::log(Fm<T>::div(ap + s, c));
     }
     return T(0.5) * (p * s + copysign(c2 * ash, p));
 }
 
-// p1 >= p0 with G_c(p1) - G_c(p0) = K.  Small kicks (K << s0^2) use the
-// series inverse of the integral around p0 (alpha = p0/s0, gamma = c^2/s0^2,
-// kappa = K/s0^2):
-//   dp/s0 = k - a/2 k^2 + (a^2/2 - g/6) k^3 + (-5/8 a^3 + 13/24 a g) k^4 + O(k^5);
-// otherwise (and always in double) Newton on G, bracketed by the bounds
-// sqrt(p^2+c^2) >= |p| (c = 0 solution) and >= c (p0 + K/c).
+// p1 >= p0 with G_c(p1) - G_c(p0) = K.
+//  - c = 0: closed form, p1|p1| = p0|p0| + 2K.
+//  - small kicks (kappa = K/s0^2 < 1/4): series inverse of the integral around
+//    p0 (alpha = p0/s0, gamma = c^2/s0^2),
+//      dp/s0 = k - a/2 k^2 + (a^2/2 - g/6) k^3 + (-5/8 a^3 + 13/24 a g) k^4 + O(k^5),
+//    used as is in float when kappa < 0.02 (truncation below float rounding),
+//    else refined by a few Newton steps on G;
+//  - large kicks: Newton on G from the upper bound min(c = 0 solution,
+//    p0 + K/c), bracketed by bisection (G is monotone).
+// Newton stops when the step falls below a few ulps of p or of c (the
+// rounding floor of G differences), or at the iteration cap.
 template <typename T>
-__device__ __forceinline__ T fast_advance(T c2, T p0, T K) {
+__device__ __forceinline__ T fast_advance(T c2, T p0, T K, int* iters = nullptr) {
     if (!(K > T(0))) return p0;
     const T eps = Eps<T>::v;
-    T s0 = sqrt(p0 * p0 + c2);
-    T inv_s0 = T(1) / s0;
-    T kap = K * inv_s0 * inv_s0;
-    T p;
-    bool series = kap < T(0.25);
-    if (series) {
-        T al = p0 * inv_s0, ga = c2 * inv_s0 * inv_s0;
-        T c4 = T(-0.625) * al * al * al + T(13.0 / 24.0) * al * ga;
-        T c3 = T(0.5) * al * al - ga * T(1.0 / 6.0);
-        T d = kap * (T(1) + kap * (T(-0.5) * al + kap * (c3 + kap * c4)));
-        p = p0 + s0 * d;
-        if (sizeof(T) == 4 && kap < T(0.02)) return p;
-    }
-    T c = sqrt(c2);
-    T Gt = G_of(c2, c, p0, s0) + K;
-    T Q = T(0.5) * p0 * fabs(p0) + K;
-    T hi = (Q >= T(0)) ? sqrt(T(2) * Q) : -sqrt(-T(2) * Q);
-    if (c2 > T(0)) hi = fmin(hi, p0 + K / c);
+    const bool f32 = sizeof(T) == 4;
+    const T Q = T(0.5) * p0 * fabs(p0) + K;
+    const T pc0 = (Q >= T(0)) ? Fm<T>::sqrt(T(2) * Q) : -Fm<T>::sqrt(-T(2) * Q);
+    if (c2 == T(0)) return pc0;
+    const T s0 = Fm<T>::sqrt(p0 * p0 + c2);
+    const T inv_s0 = Fm<T>::rcp(s0);
+    const T kap = K * inv_s0 * inv_s0;
+    const T c = Fm<T>::sqrt(c2);
+    T hi = fmin(pc0, p0 + Fm<T>::div(K, c));
     T lo = p0;
-    if (!series || !(p > lo && p <= hi)) p = hi;
-    for (int it = 0; it < 40; ++it) {
-        T s = sqrt(p * p + c2);
-        T r = G_of(c2, c, p, s) - Gt;
-        if (r > T(0)) hi = p;
-        else if (r < T(0)) lo = p;
-        else break;
-        T pn = (s > T(0)) ? p - r / s : T(0.5) * (lo + hi);
-        if (!(pn > lo && pn < hi)) pn = T(0.5) * (lo + hi);
-        T dl = fabs(pn - p);
-        p = pn;
-        if (dl <= T(4) * eps * fabs(pn) || hi - lo <= T(4) * eps * fmax(fabs(lo), fabs(hi))) break;
+    T p = hi;
+    int nmax = f32 ? 12 : 60;
+    if (kap < T(0.25)) {
+        const T al = p0 * inv_s0, ga = c2 * inv_s0 * inv_s0;
+        const T c4 = T(-0.625) * al * al * al + T(13.0 / 24.0) * al * ga;
+        const T c3 = T(0.5) * al * al - ga * T(1.0 / 6.0);
+        const T d = kap * (T(1) + kap * (T(-0.5) * al + kap * (c3 + kap * c4)));
+        const T ps = p0 + s0 * d;
+        if (f32 && kap < T(0.02)) return ps;
+        if (ps > lo && ps <= hi) p = ps;
+        nmax = f32 ? 4 : 6;
     }
+    const T Gt = G_of(c2, c, p0, s0) + K;
+    // rounding floor of a Newton step: G differences carry ~eps (|p| + c) / s
+    const T tol_rel = f32 ? T(8) * eps : T(4) * eps;
+    // A step leaving the bracket first lands on the bound it crossed (the
+    // c = 0 bound is often within rounding of the root when c << |p|); a
+    // second exit in a row bisects.
+    bool clamped = false;
+    int it = 0;
+    for (; it < nmax; ++it) {
+        const T s = Fm<T>::sqrt(p * p + c2);
+        const T r = G_of(c2, c, p, s) - Gt;
+        if (r == T(0)) break;
+        if (r > T(0)) hi = p;
+        else lo = p;
+        const T step = Fm<T>::div(r, s);
+        T pn = p - step;
+        if (fabs(step) <= tol_rel * (fabs(p) + c)) {  // converged: accept the last step
+            p = pn;
+            break;
+        }
+        if (!(pn > lo && pn < hi)) {
+            pn = clamped ? T(0.5) * (lo + hi) : (pn >= hi ? hi : lo);
+            clamped = true;
+        } else {
+            clamped = false;
+        }
+        p = pn;
+    }
+    if (iters) *iters += it + 1;
     return p;
 }
 
 // Eq. (A2a) in 1D3V: E along x, so v moves along x with c^2 = v_perp^2 fixed;
 // p = sign(a) v_x obeys dp/dt = |a| beta(sqrt(p^2 + c^2)) with a frozen.
 template <int BK, typename T>
-__device__ __forceinline__ T kick1d(T vx, T c2, T a, T dt, T u, T u2, bool uinf) {
+__device__ __forceinline__ T kick1d(T vx, T c2, T a, T dt, T u, T u2, bool uinf, int* iters = nullptr) {
     if (a == T(0)) return vx;
     if (uinf) return vx + a * dt;  // beta == 1: standard leapfrog
     if (BK == kBetaStep) {
@@ -167,30 +242,30 @@ __device__ __forceinline__ T kick1d(T vx, T c2, T a, T dt, T u, T u2, bool uinf)
     T p0 = sg * vx;
     T p1;
     if (BK == kBetaSmooth) {
-        p1 = fast_advance(c2 + u2, p0, A * u * dt);
+        p1 = fast_advance(c2 + u2, p0, A * u * dt, iters);
     } else if (c2 >= u2) {
-        p1 = fast_advance(c2, p0, A * u * dt);
+        p1 = fast_advance(c2, p0, A * u * dt, iters);
     } else {
         // Eq. (11b): fast toward the band, slow inside |p| <= ps, fast beyond
-        T ps = sqrt(u2 - c2);
+        T ps = Fm<T>::sqrt(u2 - c2);
         T p = p0, rem = dt;
         bool done = false;
         p1 = p0;
         if (p < -ps) {
-            T c = sqrt(c2);
-            T s = sqrt(p * p + c2);
+            T c = Fm<T>::sqrt(c2);
+            T s = Fm<T>::sqrt(p * p + c2);
             T Kneed = G_of(c2, c, -ps, u) - G_of(c2, c, p, s);
             T Kav = A * u * rem;
             if (Kneed >= Kav) {
-                p1 = fast_advance(c2, p, Kav);
+                p1 = fast_advance(c2, p, Kav, iters);
                 done = true;
             } else {
-                rem -= Kneed / (A * u);
+                rem -= Fm<T>::div(Kneed, A * u);
                 p = -ps;
             }
         }
         if (!done && p <= ps) {
-            T tb = (ps - p) / A;
+            T tb = Fm<T>::div(ps - p, A);
             if (tb >= rem) {
                 p1 = p + A * rem;
                 done = true;
@@ -199,7 +274,7 @@ __device__ __forceinline__ T kick1d(T vx, T c2, T a, T dt, T u, T u2, bool uinf)
                 p = ps;
             }
         }
-        if (!done) p1 = fast_advance(c2, p, A * u * rem);
+        if (!done) p1 = fast_advance(c2, p, A * u * rem, iters);
     }
     return sg * p1;
 }
@@ -230,47 +305,55 @@ template <> struct PosT<double> {
 };
 
 // ---------------------------------------------------------------------------
-// Wavefront reductions (wave64).
+// Wavefront reductions (wave64) with DPP lane permutations: quad swaps, row
+// rotations, then the row broadcasts that carry row sums into lane 63.  A
+// double moves as its two 32-bit halves; no LDS traffic.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
-    return v;
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int plo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+    const int phi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(phi, plo);
 }
 
-// CIC deposit of (w0 -> node n, w1 -> node n+1) from every lane into an LDS
-// FP64 grid.  When the wave's nodes fall in a window of five (cell-sorted
-// particles), the window is summed across the wave first and one lane adds
-// it; otherwise each lane adds its own pair.
+// Sum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x124, 0xf>(v);  // row_ror:4
+    v += dpp_f64<0x128, 0xf>(v);  // row_ror:8
+    v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// CIC deposit of (w0 -> node n, w1 -> node n+1) from every valid lane into an
+// LDS FP64 grid.  Cell-sorted waves hold few distinct nodes: the lanes of one
+// node are summed across the wave and one lane adds the pair, for up to
+// kGroups nodes; lanes left over (wide waves) add their own pair, where
+// same-address conflicts are then rare.
+constexpr int kGroups = 6;
 __device__ __forceinline__ void wave_deposit(double* Ql, bool valid, int n, double w0, double w1) {
-    int nmin = wave_min(valid ? n : 0x7fffffff);
-    if (nmin == 0x7fffffff) return;
-    int nmax = wave_max(valid ? n : -0x7fffffff);
-    if (nmax - nmin <= 3) {
-        int k = valid ? n - nmin : -10;
-        double acc[5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            double a = (k == j) ? w0 : 0.0;
-            a += (k + 1 == j) ? w1 : 0.0;
-            acc[j] = wave_sum(a);
+    const int lane = threadIdx.x & 63;
+    uint64_t act = __ballot(valid);
+    for (int g = 0; g < kGroups && act; ++g) {
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const int key = __builtin_amdgcn_readlane(n, leader);
+        const bool mine = ((act >> lane) & 1) && n == key;
+        const uint64_t m = __ballot(mine);
+        if (__popcll(m) == 1) break;  // singletons: cheaper as direct atomics
+        const double s0 = wave_sum(mine ? w0 : 0.0);
+        const double s1 = wave_sum(mine ? w1 : 0.0);
+        if (lane == leader) {
+            atomicAdd(&Ql[key], s0);
+            atomicAdd(&Ql[key + 1], s1);
         }
-        if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-            for (int j = 0; j < 5; ++j)
-                if (acc[j] != 0.0) atomicAdd(&Ql[nmin + j], acc[j]);
-        }
-    } else if (valid) {
+        act &= ~m;
+    }
+    if ((act >> lane) & 1) {
         atomicAdd(&Ql[n], w0);
         atomicAdd(&Ql[n + 1], w1);
     }

@@ -21,6 +21,14 @@ from parity_util import (cells_agree, oracle_state, print_case, push_oracle_to_g
 pytestmark = pytest.mark.gpu
 
 
+# The exact-integral velocity map inverts G_c(p) = (p s + c^2 asinh(p/c))/2;
+# in FP64 both sides carry an absolute velocity error of order
+# eps * (p0^2 + c^2) / max(s1, c), up to ~1e-12 v_te for particles slowed
+# through zero with a small perpendicular speed.  Velocities are compared
+# with that absolute floor (positions inherit it times beta dt/dx).
+V_ABS_TOL = 1e-11
+
+
 def _compare_step(sim, run, r=0, tol_q=1e-12, tol_x=1e-11, tol_v=1e-11, exact_counts=True):
     g = sim.grid(r)
     o = run.grid()
@@ -35,7 +43,7 @@ def _compare_step(sim, run, r=0, tol_q=1e-12, tol_x=1e-11, tol_v=1e-11, exact_co
             assert len(xg) == len(xo), (s, len(xg), len(xo))
         n = min(len(xg), len(xo))
         np.testing.assert_allclose(xg[:n], xo[:n], rtol=0, atol=tol_x)
-        np.testing.assert_allclose(vxg[:n], vxo[:n], rtol=tol_v, atol=tol_v * 1e-3)
+        np.testing.assert_allclose(vxg[:n], vxo[:n], rtol=tol_v, atol=V_ABS_TOL)
         ok, _ = cells_agree(xg[:n], xo[:n], max(tol_x, 1e-12))
         assert ok, s
     return st
