@@ -2,15 +2,19 @@
 
 Workload: the 1D argon sheath at production shape -- 2048 cells over 1024
 Debye lengths, 1000 macroparticles per cell per species (4,096,000
-particles), Te = 1 eV, Ti = 0.05 eV, speed limit u = 2 v_ti, FP32 particles
-(int32 fixed-point positions, float velocities) with FP64 grids.  A step is
-one pass of the whole hot path: push + beta-weighted deposit, wall
-absorption, source injection, field solve and the periodic cell sort.
+particles), Te = 1 eV, Ti = 0.05 eV, speed limit u = 2 v_ti, dt = 1/omega_pi,
+FP32 particles (int32 fixed-point positions, float velocities) with FP64
+grids.  A step is one pass of the whole hot path: push + beta-weighted
+deposit, wall absorption, source injection, field solve, and the cell sort
+every 16 steps.  Steps replay as HIP graphs of 16 steps.
 
 Prints one JSON line.  `value` is live particle pushes per second over the
-timed steps (whole step time); `roofline` prices the dominant kernel
-(push + deposit) by its algorithmic bytes over its average launch time,
-measured with HIP events on the launch stream inside the timed region.
+timed steps (whole-step time, host clock around the timed region with device
+synchronisation on both sides).  `roofline` prices the dominant kernel
+(push + deposit) by its algorithmic bytes (20 B per live particle: read x,
+v_x, v_perp^2; write x, v_x) over its average launch time, measured with HIP
+events captured around each push launch on the launch stream inside the
+timed region.  `cpu_baseline` is the FP64 oracle on the host.
 """
 from __future__ import annotations
 
@@ -26,8 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-pushes/s per GPU; time-to-steady-sheath, batched+warm-start vs plain"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_PUSH_F32 = 20  # read x, vx, vperp^2 (12 B); write x, vx (8 B)
-BYTES_PER_PUSH_F64 = 40
+BYTES_PER_PUSH = {"f32": 20, "f64": 40}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_deposit_traffic.json")
 
 
 def cpu_baseline(cfg: dict, budget_s: float = 12.0) -> dict:
@@ -44,64 +48,73 @@ def cpu_baseline(cfg: dict, budget_s: float = 12.0) -> dict:
             break
     dt = time.perf_counter() - t0
     return {"value": n0 * steps / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the same sheath ({n0} particles), FP64 C oracle, 1 thread"}
+            "sample": f"{steps} steps of the same sheath from its cold load ({n0} particles), "
+                      f"FP64 C oracle, one thread"}
+
+
+def run_timed(cfg, args, steps, warmup):
+    import torch
+    from paper_1511_08225_amd import slpic
+    sim = slpic.Sim(cfg, precision=args.precision, sort_every=args.sort_every, chunk=args.chunk,
+                    graph_steps=args.graph_steps)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.profile(True)  # events around each push launch
+    p0 = sim.pushed_total()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pushes = sim.pushed_total() - p0
+    prof = sim.profile_read()["push"]
+    st = sim.status(0)
+    sim.close()
+    return pushes, t1 - t0, prof, st
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=1024)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--u", type=float, default=2.0, help="speed limit in ion thermal speeds (inf = PIC)")
     ap.add_argument("--ppc", type=int, default=1000)
     ap.add_argument("--sort-every", type=int, default=16)
+    ap.add_argument("--graph-steps", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=256, help="slots per push wavefront")
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default="", help="JSON with measured HBM bytes per push launch")
+    ap.add_argument("--no-hbm-variant", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
+    g = args.graph_steps
+    steps = max(g, (args.steps // g) * g) if g else args.steps
+    warmup = (args.warmup // g) * g if g else args.warmup
 
-    import torch
     import workloads
-    from paper_1511_08225_amd import slpic
-
     cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc, sort_every=args.sort_every)
-    sim = slpic.Sim(cfg, precision=args.precision, sort_every=args.sort_every)
-    torch.cuda.synchronize()
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-
-    sim.profile(True)
-    p0 = sim.pushed_total()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pushes = sim.pushed_total() - p0
-    prof = sim.profile_read()
-    sim.profile(False)
-    st = sim.status(0)
-
-    elapsed = t1 - t0
-    value = pushes / elapsed
-    bpp = BYTES_PER_PUSH_F32 if args.precision == "f32" else BYTES_PER_PUSH_F64
-    push_ms = prof["push"]["ms"] / max(prof["push"]["launches"], 1)
-    bytes_per_launch = bpp * pushes / max(prof["push"]["launches"], 1)
+    pushes, elapsed, prof, st = run_timed(cfg, args, steps, warmup)
+    bpp = BYTES_PER_PUSH[args.precision]
+    launches = max(prof["launches"], 1)
+    push_ms = prof["ms"] / launches
+    bytes_per_launch = bpp * pushes / launches
     achieved = bytes_per_launch / (push_ms * 1e-3) / 1e9
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("workload") == "production_sheath" and t.get("chunk") == args.chunk:
+            traffic = t.get("bytes_per_launch")
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": pushes / elapsed,
         "unit": "particle-pushes/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -109,8 +122,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": (f"1D3V argon sheath, 2048 cells over 1024 Debye lengths, {args.ppc} particles/cell/"
-                         f"species ({2 * 2048 * args.ppc} particles), Te/Ti=20, u={args.u} v_ti, "
-                         f"dt={cfg['dt']:.4g}/omega_pe, sort every {args.sort_every} steps"),
+                         f"species ({2 * 2048 * args.ppc} particles at load), Te/Ti=20, u={args.u} v_ti, "
+                         f"dt={cfg['dt']:.4g}/omega_pe, cell sort every {args.sort_every} steps"),
             "particles": 2 * 2048 * args.ppc,
             "u_over_vti": args.u,
             "dt": cfg["dt"],
@@ -125,11 +138,22 @@ def main() -> int:
             "kernel": "k_push_deposit",
             "bytes_per_push": bpp,
             "avg_launch_ms": push_ms,
+            "launches": prof["launches"],
         },
-        "kernel_ms_per_step": {k: v["ms"] / max(v["launches"], 1) for k, v in prof.items()},
         "wall_potential": st["wall_potential"],
         "error_flags": st["error_flags"],
     }
+    if not args.no_hbm_variant and args.ppc == 1000:
+        # the same sheath with 10x the particles per cell (41M particles,
+        # 655 MB of particle state: larger than the 256 MB Infinity Cache)
+        cfg10 = workloads.production_sheath(u_over_vti=args.u, ppc=10 * args.ppc, sort_every=args.sort_every)
+        p10, e10, prof10, _ = run_timed(cfg10, args, 4 * g if g else 64, g if g else 16)
+        l10 = max(prof10["launches"], 1)
+        ms10 = prof10["ms"] / l10
+        a10 = bpp * p10 / l10 / (ms10 * 1e-3) / 1e9
+        line["hbm_variant"] = {"particles": 2 * 2048 * 10 * args.ppc, "value": p10 / e10,
+                               "push_avg_launch_ms": ms10, "achieved_GBs": a10,
+                               "frac": a10 / HBM_PEAK_GBS}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

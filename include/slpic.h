@@ -176,11 +176,13 @@ int slpic_sort_now(void* ctx, void* stream);
 int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, int64_t* n);
 
 /* Kernel timing with HIP events on the launch stream (for roofline
- * accounting).  enable != 0 switches slpic_step to direct launches with an
- * event pair around every push-deposit, inject, field and sort launch and
- * clears previous records.  slpic_profile_read (sync) returns the summed
- * milliseconds and launch counts per kernel class in the order push, inject,
- * field, sort (arrays of 4). */
+ * accounting).  enable is a bitmask of kernel classes (bit 0 push-deposit,
+ * bit 1 source injection, bit 2 field solve, bit 3 sort; 0 = off): an event
+ * pair is recorded around every launch of an enabled class in slpic_step (inside
+ * the captured graphs when tuning.graph_steps > 0, each replay of a timed
+ * region using its own graph and events) and clears previous records.
+ * slpic_profile_read (sync) returns the summed milliseconds and launch
+ * counts per kernel class in that order (arrays of 4). */
 int slpic_profile(void* ctx, int32_t enable);
 int slpic_profile_read(void* ctx, double* h_ms, int64_t* h_launches);
 

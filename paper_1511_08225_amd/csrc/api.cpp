@@ -64,8 +64,8 @@ int ceil_log2(int64_t v) {
 }
 
 struct Layout {
-    size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, phi, Qacc, Qlast, hist,
-        totals, btot, history, total;
+    size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
+        totals, counts, inj, btot, history, total;
 };
 
 struct Plan {
@@ -89,12 +89,12 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         t.sort_tile < 0)
         return SLPIC_EINVAL;
     if (t.block == 0) t.block = 256;
-    if (t.chunk == 0) t.chunk = t.block * (t.precision == SLPIC_F32 ? 8 : 4);
+    if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
     if (t.sort_tile == 0) t.sort_tile = 16384;
     if (t.block < 64 || t.block > 1024 || t.block % 64) return SLPIC_EINVAL;
-    {   // particles per thread in the push: chunk = block * P, P in {1, 2, 4, 8}
-        const int per = t.chunk / t.block;
-        if (t.chunk % t.block || (per != 1 && per != 2 && per != 4 && per != 8)) return SLPIC_EINVAL;
+    {   // one wavefront per push chunk: chunk = 64 * P, P in {1, 2, 4, 8}
+        const int per = t.chunk / 64;
+        if (t.chunk % 64 || (per != 1 && per != 2 && per != 4 && per != 8)) return SLPIC_EINVAL;
     }
     if (t.sort_every > 0 && t.graph_steps > 0 && t.graph_steps % t.sort_every)
         t.graph_steps = (t.graph_steps / t.sort_every + 1) * t.sort_every;
@@ -169,9 +169,11 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     for (int r = 0; r < nruns; ++r) {
         P.run_chunk0[r] = (int)P.chunks.size();
         for (int s = 0; s < 2; ++s) {
-            const RunInfo& R = P.runs[r];
+            RunInfo& R = P.runs[r];
+            R.chunk0[s] = (int32_t)P.chunks.size();
             for (int64_t b = 0; b < R.cap[s]; b += t.chunk)
                 P.chunks.push_back(Chunk{r, s, b, std::min<int64_t>(b + t.chunk, R.cap[s])});
+            R.nchunk[s] = (int32_t)P.chunks.size() - R.chunk0[s];
             for (int k = 0; k < R.ntiles[s]; ++k) {
                 int64_t b = (int64_t)k * t.sort_tile;
                 P.tiles.push_back(Tile{r, s, k, 0, b, std::min<int64_t>(b + t.sort_tile, R.cap[s])});
@@ -200,11 +202,14 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     }
     L.perm = take(sizeof(int32_t) * P.total_slots);
     L.E = take(sizeof(double) * P.total_nodes);
+    L.E32 = take(sizeof(float) * P.total_nodes);
     L.phi = take(sizeof(double) * P.total_nodes);
     L.Qacc = take(sizeof(double) * 2 * P.total_nodes);
     L.Qlast = take(sizeof(double) * 2 * P.total_nodes);
     L.hist = take(sizeof(int) * P.hist_entries);
     L.totals = take(sizeof(int64_t) * 2 * nruns);
+    L.counts = take(sizeof(int2) * kMaxSpecies * kCountSlots * nruns);
+    L.inj = take(sizeof(InjectPlan) * nruns);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
     L.total = o;
@@ -213,6 +218,14 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
 
 struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
+};
+
+// A captured block of steps with its own event pairs (profiling under graph
+// replay: every replay in a timed region uses a fresh block, so no event is
+// overwritten before it is read).
+struct ProfGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<EventPair> ev[4];
 };
 
 struct Context {
@@ -225,8 +238,13 @@ struct Context {
     hipGraphExec_t gexec = nullptr;
     int graph_len = 0;
     bool prof = false;
+    int prof_mask = 0;  // kernel classes timed: bit k = class k
     std::vector<EventPair> ev[4];
     size_t ev_used[4] = {0, 0, 0, 0};
+    std::vector<ProfGraph> pgraphs;
+    size_t pg_used = 0;
+    ProfGraph* capturing = nullptr;  // events recorded during a capture go here
+    bool pgraph_failed = false;
     ~Context() {
         if (gexec) hipGraphExecDestroy(gexec);
         for (auto& v : ev)
@@ -234,6 +252,14 @@ struct Context {
                 if (e.a) hipEventDestroy(e.a);
                 if (e.b) hipEventDestroy(e.b);
             }
+        for (auto& g : pgraphs) {
+            if (g.exec) hipGraphExecDestroy(g.exec);
+            for (auto& v : g.ev)
+                for (auto& e : v) {
+                    if (e.a) hipEventDestroy(e.a);
+                    if (e.b) hipEventDestroy(e.b);
+                }
+        }
     }
 };
 
@@ -249,22 +275,33 @@ void l_load(Context* c, hipStream_t s) {
     else launch_load_f64(c->a, (int)c->P.chunks.size(), 256, s);
 }
 void l_push(Context* c, bool push, hipStream_t s) {
-    const int per = c->P.tun.chunk / c->P.tun.block;
+    const int per = c->P.tun.chunk / 64;
     if (prec(c) == SLPIC_F32)
-        launch_push_f32(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
+        launch_push_f32(push, per, c->a, (int)c->P.chunks.size(), 64, 0, s);
     else
-        launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, c->push_lds, s);
+        launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), 64, 0, s);
 }
+constexpr int kInjectGroups = 8;  // workgroups per run generating source particles
 void l_inject(Context* c, hipStream_t s) {
-    if (prec(c) == SLPIC_F32) launch_inject_f32(c->a, c->P.nruns, 256, c->inject_lds, s);
-    else launch_inject_f64(c->a, c->P.nruns, 256, c->inject_lds, s);
+    if (prec(c) == SLPIC_F32) launch_inject_f32(c->a, c->P.nruns, kInjectGroups, c->inject_lds, s);
+    else launch_inject_f64(c->a, c->P.nruns, kInjectGroups, c->inject_lds, s);
 }
 
 // timed launch wrapper: class k in {0 push, 1 inject, 2 field, 3 sort}
 template <typename F>
 int timed(Context* c, int k, hipStream_t s, F&& f) {
-    if (!c->prof) {
+    if (!c->prof || !((c->prof_mask >> k) & 1)) {
         f();
+        return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+    }
+    if (c->capturing) {  // event record nodes inside the graph being captured
+        EventPair e;
+        HIP_TRY(hipEventCreate(&e.a));
+        HIP_TRY(hipEventCreate(&e.b));
+        c->capturing->ev[k].push_back(e);
+        HIP_TRY(hipEventRecord(e.a, s));
+        f();
+        HIP_TRY(hipEventRecord(e.b, s));
         return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
     }
     if (c->ev_used[k] == c->ev[k].size()) {
@@ -297,14 +334,15 @@ int one_step(Context* c, int64_t local_step, hipStream_t s) {
     int rc;
     if ((rc = timed(c, 0, s, [&] { l_push(c, true, s); }))) return rc;
     if ((rc = timed(c, 1, s, [&] { l_inject(c, s); }))) return rc;
-    if ((rc = timed(c, 2, s, [&] { launch_field(c->a, c->P.nruns, 1, c->field_lds, s); }))) return rc;
+    if ((rc = timed(c, 2, s, [&] { launch_field_step(c->a, c->P.nruns, c->field_lds, s); }))) return rc;
     const int se = c->P.tun.sort_every;
     if (se > 0 && (local_step + 1) % se == 0)
         if ((rc = do_sort(c, s))) return rc;
     return SLPIC_OK;
 }
 
-int build_graph(Context* c, hipStream_t s) {
+// Capture graph_steps steps into *out (with event records when profiling).
+int capture_steps(Context* c, hipStream_t s, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
     int rc = SLPIC_OK;
@@ -312,16 +350,46 @@ int build_graph(Context* c, hipStream_t s) {
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc != SLPIC_OK || e != hipSuccess) {
         if (g) hipGraphDestroy(g);
+        (void)hipGetLastError();
         return rc != SLPIC_OK ? rc : SLPIC_EHIP;
     }
-    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->gexec = nullptr;
+        *out = nullptr;
         return SLPIC_EHIP;
     }
-    c->graph_len = c->P.tun.graph_steps;
     return SLPIC_OK;
+}
+
+int build_graph(Context* c, hipStream_t s) {
+    int rc = capture_steps(c, s, &c->gexec);
+    if (rc == SLPIC_OK) c->graph_len = c->P.tun.graph_steps;
+    return rc;
+}
+
+// The next unused profiling graph (captured on first use).  Returns nullptr
+// if event records cannot be captured; the caller then launches directly.
+ProfGraph* next_prof_graph(Context* c, hipStream_t s) {
+    if (c->pgraph_failed) return nullptr;
+    if (c->pg_used == c->pgraphs.size()) {
+        c->pgraphs.emplace_back();
+        ProfGraph* pg = &c->pgraphs.back();
+        c->capturing = pg;
+        int rc = capture_steps(c, s, &pg->exec);
+        c->capturing = nullptr;
+        if (rc != SLPIC_OK) {
+            for (auto& v : pg->ev)
+                for (auto& e : v) {
+                    if (e.a) hipEventDestroy(e.a);
+                    if (e.b) hipEventDestroy(e.b);
+                }
+            c->pgraphs.pop_back();
+            c->pgraph_failed = true;
+            return nullptr;
+        }
+    }
+    return &c->pgraphs[c->pg_used++];
 }
 
 Context* ctx_of(void* p) { return static_cast<Context*>(p); }
@@ -383,11 +451,14 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     }
     a.perm = (int32_t*)(w + L.perm);
     a.E = (double*)(w + L.E);
+    a.E32 = (float*)(w + L.E32);
     a.phi = (double*)(w + L.phi);
     a.Qacc = (double*)(w + L.Qacc);
     a.Qlast = (double*)(w + L.Qlast);
     a.hist = (int*)(w + L.hist);
     a.totals = (int64_t*)(w + L.totals);
+    a.counts = (int2*)(w + L.counts);
+    a.inj = (InjectPlan*)(w + L.inj);
     a.history = (double*)(w + L.history);
     c->btot = (long long*)(w + L.btot);
     const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
@@ -436,19 +507,28 @@ int slpic_step(void* ctx, int32_t nsteps, void* stream) {
     if (!c || nsteps < 0) return SLPIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int se = c->P.tun.sort_every;
-    const bool graphs = c->P.tun.graph_steps > 0 && !c->prof && s != nullptr;
+    const bool graphs = c->P.tun.graph_steps > 0 && s != nullptr;
     int32_t done = 0;
     while (done < nsteps) {
         const int gl = c->P.tun.graph_steps;
         if (graphs && nsteps - done >= gl && (se == 0 || c->steps_done % se == 0)) {
-            if (!c->gexec) {
-                int rc = build_graph(c, s);
-                if (rc) return rc;
+            hipGraphExec_t ex = nullptr;
+            if (c->prof) {
+                ProfGraph* pg = next_prof_graph(c, s);
+                if (pg) ex = pg->exec;
+            } else {
+                if (!c->gexec) {
+                    int rc = build_graph(c, s);
+                    if (rc) return rc;
+                }
+                ex = c->gexec;
             }
-            HIP_TRY(hipGraphLaunch(c->gexec, s));
-            c->steps_done += gl;
-            done += gl;
-            continue;
+            if (ex) {
+                HIP_TRY(hipGraphLaunch(ex, s));
+                c->steps_done += gl;
+                done += gl;
+                continue;
+            }
         }
         int rc = one_step(c, c->steps_done, s);
         if (rc) return rc;
@@ -634,8 +714,21 @@ int slpic_profile(void* ctx, int32_t enable) {
     Context* c = ctx_of(ctx);
     if (!c) return SLPIC_EINVAL;
     HIP_TRY(hipDeviceSynchronize());
-    c->prof = enable != 0;
+    if (c->prof_mask != (enable & 15)) {  // captured profiling graphs hold the old event layout
+        for (auto& g : c->pgraphs) {
+            if (g.exec) hipGraphExecDestroy(g.exec);
+            for (auto& v : g.ev)
+                for (auto& e : v) {
+                    if (e.a) hipEventDestroy(e.a);
+                    if (e.b) hipEventDestroy(e.b);
+                }
+        }
+        c->pgraphs.clear();
+    }
+    c->prof = (enable & 15) != 0;
+    c->prof_mask = enable & 15;
     for (auto& u : c->ev_used) u = 0;
+    c->pg_used = 0;
     return SLPIC_OK;
 }
 
@@ -645,13 +738,22 @@ int slpic_profile_read(void* ctx, double* h_ms, int64_t* h_launches) {
     HIP_TRY(hipDeviceSynchronize());
     for (int k = 0; k < 4; ++k) {
         double sum = 0.0;
+        int64_t n = 0;
         for (size_t i = 0; i < c->ev_used[k]; ++i) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, c->ev[k][i].a, c->ev[k][i].b));
             sum += ms;
+            ++n;
         }
+        for (size_t g = 0; g < c->pg_used; ++g)
+            for (auto& e : c->pgraphs[g].ev[k]) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
+                sum += ms;
+                ++n;
+            }
         h_ms[k] = sum;
-        h_launches[k] = (int64_t)c->ev_used[k];
+        h_launches[k] = n;
     }
     return SLPIC_OK;
 }

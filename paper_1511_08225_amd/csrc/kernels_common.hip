@@ -5,6 +5,7 @@
 
 #include "launch.h"
 #include "slpic_device.h"
+#include "field.inc"
 
 namespace slpic {
 
@@ -22,120 +23,41 @@ __global__ void k_init_state(KArgs a, int nruns) {
     }
     st->step = 0;
     st->pushed_total = 0;
+    for (int j = 0; j < kMaxSpecies * kCountSlots; ++j)
+        a.counts[(int64_t)r * kMaxSpecies * kCountSlots + j] = make_int2(0, 0);
     st->acc_e = 0.0;
     st->phi_w = 0.0;
     st->error = 0;
 }
 
-// Block-wide exclusive scans of one value per thread, in thread order
-// (prefix) or reverse thread order (suffix): wave64 shuffles, then the wave
-// totals in LDS.  Fixed summation order, so results are reproducible.
-template <typename V>
-__device__ V block_scan(V v, V* tmp, bool suffix) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    V inc = v;
-    if (!suffix) {
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            V t = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += t;
-        }
-    } else {
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            V t = __shfl_down(inc, d, 64);
-            if (lane + d < 64) inc += t;
-        }
-    }
-    V exc = suffix ? __shfl_down(inc, 1, 64) : __shfl_up(inc, 1, 64);
-    if (suffix ? lane == 63 : lane == 0) exc = V(0);
-    if (suffix ? lane == 0 : lane == 63) tmp[w] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        V run = V(0);
-        for (int k = 0; k < nw; ++k) {
-            int kk = suffix ? nw - 1 - k : k;
-            V t = tmp[kk];
-            tmp[kk] = run;
-            run += t;
-        }
-        tmp[nw] = run;
-    }
-    __syncthreads();
-    V r = tmp[w] + exc;
-    __syncthreads();
-    return r;
+__global__ void k_field(KArgs a, int advance) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* D = (double*)smem;
+    field_solve(a, blockIdx.x, advance, D, D + a.runs[blockIdx.x].nodes);
 }
 
-// Field solve of one run (one workgroup).  Charge Q_j = sum_s Q_{s,j};
-// rho_j = Q_j/dV_j with half volumes at both ends.  With the symmetry plane
-// at node 0 and phi = 0 at node nx, the three-point system
-//   -2(phi_1 - phi_0)/dx^2 = rho_0,  -(phi_{j+1} - 2 phi_j + phi_{j-1})/dx^2 = rho_j
-// has the exact two-pass solution
-//   D_j = phi_j - phi_{j+1} = dx * sum_{i<=j} Q_i        (Gauss's law)
-//   phi_j = sum_{k=j}^{nx-1} D_k,
-// computed as a prefix scan and a suffix scan.  E_j = -(phi_{j+1} -
-// phi_{j-1})/(2dx) = (D_{j-1} + D_j)/(2dx), E_0 = 0, and the one-sided
-// second-order difference at the wall, E_nx = (3 D_{nx-1} - D_{nx-2})/(2dx).
-__global__ void k_field(KArgs a, int advance) {
+// The step's field kernel: apply the source bookkeeping of the step to the
+// run state, clear the push counters, then solve for phi^{n+1}, E^{n+1}.
+__global__ void k_field_step(KArgs a) {
     const int run = blockIdx.x;
-    const RunInfo& R = a.runs[run];
     RunState* st = a.state + run;
-    const int nx = R.nx, nodes = R.nodes;
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* D = (double*)smem;  // [nodes]
-    double* tmp = D + nodes;    // [nwaves + 1]
-    double* Qa = a.Qacc + 2 * R.goff;
-    double* Ql = a.Qlast + 2 * R.goff;
-    for (int j = threadIdx.x; j < nodes; j += blockDim.x) {
-        double q0 = Qa[j], q1 = Qa[nodes + j];
-        Ql[j] = q0;
-        Ql[nodes + j] = q1;
-        Qa[j] = 0.0;
-        Qa[nodes + j] = 0.0;
-        D[j] = q0 + q1;
-    }
-    __syncthreads();
-    const int per = (nx + blockDim.x - 1) / blockDim.x;
-    const int j0 = threadIdx.x * per, j1 = min(j0 + per, nx);
-    {   // prefix: D_j = dx * sum_{i<=j} Q_i
-        double loc = 0.0;
-        for (int j = j0; j < j1; ++j) loc += D[j];
-        double run_s = block_scan(loc, tmp, false);
-        for (int j = j0; j < j1; ++j) {
-            run_s += D[j];
-            D[j] = R.dx * run_s;
-        }
-    }
-    __syncthreads();
-    double* phi = a.phi + R.goff;
-    {   // suffix: phi_j = sum_{k>=j} D_k
-        double loc = 0.0;
-        for (int j = j1 - 1; j >= j0; --j) loc += D[j];
-        double run_s = block_scan(loc, tmp, true);
-        for (int j = j1 - 1; j >= j0; --j) {
-            run_s += D[j];
-            phi[j] = run_s;
-        }
-    }
-    double* E = a.E + R.goff;
-    for (int j = threadIdx.x; j < nodes; j += blockDim.x) {
-        double e;
-        if (j == 0) e = 0.0;
-        else if (j < nx) e = (D[j - 1] + D[j]) / (2.0 * R.dx);
-        else e = (3.0 * D[nx - 1] - D[nx - 2]) / (2.0 * R.dx);
-        E[j] = e;
-        if (j == nx) phi[j] = 0.0;
-    }
-    __syncthreads();
     if (threadIdx.x == 0) {
-        double pw = phi[0];
-        st->phi_w = pw;
-        if (advance) {
-            a.history[(int64_t)run * kHistoryLen + (st->step % kHistoryLen)] = pw;
-            st->step += 1;
+        const InjectPlan& ip = a.inj[run];
+        for (int s = 0; s < kMaxSpecies; ++s) {
+            st->nslots[s] = ip.base[s] + ip.count[s];
+            st->injected_total[s] += ip.count[s];
+            st->absorbed_total[s] += ip.absorbed[s];
         }
+        st->pushed_total += ip.pushed;
+        st->acc_e = ip.acc_e;
+        if (ip.overflow) st->error |= 1;
     }
+    int2* cs = a.counts + (int64_t)run * kMaxSpecies * kCountSlots;
+    for (int j = threadIdx.x; j < kMaxSpecies * kCountSlots; j += blockDim.x) cs[j] = make_int2(0, 0);
+    __syncthreads();
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* D = (double*)smem;
+    field_solve(a, run, 1, D, D + a.runs[run].nodes);
 }
 
 // Exclusive scan of the sort histogram, in place, over all (run, species)
@@ -222,7 +144,10 @@ void launch_init_state(const KArgs& a, int nruns, hipStream_t s) {
     hipLaunchKernelGGL(k_init_state, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns);
 }
 void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_field, dim3(nruns), dim3(1024), lds, s, a, advance);
+    hipLaunchKernelGGL(k_field, dim3(nruns), dim3(256), lds, s, a, advance);
+}
+void launch_field_step(const KArgs& a, int nruns, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_field_step, dim3(nruns), dim3(256), lds, s, a);
 }
 int scan_blocks(int64_t n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
 void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s) {

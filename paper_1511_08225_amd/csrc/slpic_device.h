@@ -330,13 +330,19 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// CIC deposit of (w0 -> node n, w1 -> node n+1) from every valid lane into an
-// LDS FP64 grid.  Cell-sorted waves hold few distinct nodes: the lanes of one
-// node are summed across the wave and one lane adds the pair, for up to
-// kGroups nodes; lanes left over (wide waves) add their own pair, where
-// same-address conflicts are then rare.
+// CIC deposit of (w0 -> node n, w1 -> node n+1) from every valid lane into
+// an FP64 grid (LDS or global).  Cell-sorted waves hold few distinct nodes:
+// the lanes of one node are summed across the wave and one lane adds the
+// pair, for up to kGroups nodes; lanes left over (wide waves) add their own
+// pair, where same-address conflicts are then rare.
 constexpr int kGroups = 6;
-__device__ __forceinline__ void wave_deposit(double* Ql, bool valid, int n, double w0, double w1) {
+template <bool GLOBAL>
+__device__ __forceinline__ void add_f64(double* p, double v) {
+    if (GLOBAL) unsafeAtomicAdd(p, v);
+    else atomicAdd(p, v);
+}
+template <bool GLOBAL>
+__device__ __forceinline__ void wave_deposit(double* Q, bool valid, int n, double w0, double w1) {
     const int lane = threadIdx.x & 63;
     uint64_t act = __ballot(valid);
     for (int g = 0; g < kGroups && act; ++g) {
@@ -344,19 +350,26 @@ __device__ __forceinline__ void wave_deposit(double* Ql, bool valid, int n, doub
         const int key = __builtin_amdgcn_readlane(n, leader);
         const bool mine = ((act >> lane) & 1) && n == key;
         const uint64_t m = __ballot(mine);
-        if (__popcll(m) == 1) break;  // singletons: cheaper as direct atomics
+        if (__popcll(m) == 1) break;  // singletons: cheaper as direct adds
         const double s0 = wave_sum(mine ? w0 : 0.0);
         const double s1 = wave_sum(mine ? w1 : 0.0);
         if (lane == leader) {
-            atomicAdd(&Ql[key], s0);
-            atomicAdd(&Ql[key + 1], s1);
+            add_f64<GLOBAL>(&Q[key], s0);
+            add_f64<GLOBAL>(&Q[key + 1], s1);
         }
         act &= ~m;
     }
     if ((act >> lane) & 1) {
-        atomicAdd(&Ql[n], w0);
-        atomicAdd(&Ql[n + 1], w1);
+        add_f64<GLOBAL>(&Q[n], w0);
+        add_f64<GLOBAL>(&Q[n + 1], w1);
     }
+}
+
+// Orders a wave's LDS accesses: everything before is complete and visible to
+// the other lanes of the wave before anything after.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 }  // namespace slpic

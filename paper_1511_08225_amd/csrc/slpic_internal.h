@@ -11,6 +11,7 @@ constexpr int kMaxSpecies = 2;
 constexpr int kPurposeLoad = 1;
 constexpr int kPurposeInject = 2;
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
+constexpr int kCountSlots = 64;    // spread slots of the per-step particle counters
 
 // Immutable per-run parameters (device copy of the host plan).
 struct RunInfo {
@@ -32,7 +33,8 @@ struct RunInfo {
     int64_t goff;                // first node in the global node arrays
     int64_t hoff[kMaxSpecies];   // first entry of the sort histogram of (run, species)
     int32_t ntiles[kMaxSpecies]; // sort tiles of (run, species)
-    int32_t pad1[2];
+    int32_t chunk0[kMaxSpecies]; // first push chunk of (run, species)
+    int32_t nchunk[kMaxSpecies]; // push chunks of (run, species)
 };
 
 // Mutable per-run state, updated on the device.
@@ -46,6 +48,18 @@ struct alignas(64) RunState {
     double acc_e;
     double phi_w;
     int32_t error;
+    int32_t pad;
+};
+
+// Source bookkeeping of one step, computed from the push counters before the
+// new particles are written and applied to the run state after.
+struct InjectPlan {
+    int64_t base[kMaxSpecies];      // first new slot
+    int64_t count[kMaxSpecies];     // particles injected
+    int64_t absorbed[kMaxSpecies];  // particles absorbed at the wall this step
+    int64_t pushed;                 // live particles pushed this step
+    double acc_e;                   // carried fraction after this step
+    int32_t overflow;               // capacity hit
     int32_t pad;
 };
 
@@ -79,12 +93,15 @@ struct KArgs {
     Bufs bufs;
     int* cur;             // which of the two particle buffers is current
     double* E;            // node field, per run at goff
+    float* E32;           // float copy of the node field (float particles gather it)
     double* phi;          // node potential
     double* Qacc;         // deposit accumulators [run][species][nodes] at 2*goff
     double* Qlast;        // last step's charge per species, same layout
     double* history;      // wall-potential ring [run][kHistoryLen]
     int* hist;            // sort histogram, per (run, species) at hoff
     int64_t* totals;      // live slots after the sort [run][species]
+    int2* counts;         // [run][species][kCountSlots]: (absorbed, pushed) of the last push
+    struct InjectPlan* inj;  // [run]: source counts of the current step
     int32_t* perm;        // last sort's permutation (new slot -> old slot)
 };
 

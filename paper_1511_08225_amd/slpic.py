@@ -254,8 +254,11 @@ class Sim:
         return self.status(run)["wall_potential"]
 
     # ---------------------------------------------------------------- timing
-    def profile(self, enable: bool = True):
-        _check(lib().slpic_profile(self._ctx, 1 if enable else 0), "slpic_profile")
+    def profile(self, enable=True):
+        """enable: True (push kernel only), False, or a bitmask of
+        PROFILE_CLASSES (1 push, 2 inject, 4 field, 8 sort)."""
+        mask = (1 if enable else 0) if isinstance(enable, bool) else int(enable)
+        _check(lib().slpic_profile(self._ctx, mask), "slpic_profile")
 
     def profile_read(self) -> dict:
         ms = (ctypes.c_double * 4)()
