@@ -82,7 +82,7 @@ def main() -> int:
     ap.add_argument("--ppc", type=int, default=1000)
     ap.add_argument("--sort-every", type=int, default=16)
     ap.add_argument("--graph-steps", type=int, default=16)
-    ap.add_argument("--chunk", type=int, default=256, help="slots per push wavefront")
+    ap.add_argument("--chunk", type=int, default=512, help="slots per push wavefront")
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-variant", action="store_true")

@@ -95,7 +95,8 @@ typedef struct {
     int32_t sort_every;   /* stable cell sort + compaction every k steps; 0 = never  */
     int32_t sort_bucket;  /* sort key = cell / bucket; 0 = compaction only (key 0)   */
     int32_t chunk;        /* particles per push workgroup; 0 = default               */
-    int32_t block;        /* threads per push workgroup (64..1024); 0 = default      */
+    int32_t block;        /* threads per push workgroup: 64, 128, 192 or 256, one   */
+                          /* wavefront per chunk; 0 = default (128)                  */
     int32_t graph_steps;  /* steps captured per HIP graph; 0 = direct launches       */
     int32_t sort_tile;    /* particles per sort workgroup; 0 = default               */
     int32_t reserved;

@@ -65,7 +65,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
-        totals, counts, inj, btot, history, total;
+        totals, counts, push_err, inj, btot, history, total;
 };
 
 struct Plan {
@@ -88,10 +88,10 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
         t.sort_tile < 0)
         return SLPIC_EINVAL;
-    if (t.block == 0) t.block = 256;
+    if (t.block == 0) t.block = 128;
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
     if (t.sort_tile == 0) t.sort_tile = 16384;
-    if (t.block < 64 || t.block > 1024 || t.block % 64) return SLPIC_EINVAL;
+    if (t.block < 64 || t.block > 256 || t.block % 64) return SLPIC_EINVAL;  // 1..4 push waves
     {   // one wavefront per push chunk: chunk = 64 * P, P in {1, 2, 4, 8}
         const int per = t.chunk / 64;
         if (t.chunk % 64 || (per != 1 && per != 2 && per != 4 && per != 8)) return SLPIC_EINVAL;
@@ -172,7 +172,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             RunInfo& R = P.runs[r];
             R.chunk0[s] = (int32_t)P.chunks.size();
             for (int64_t b = 0; b < R.cap[s]; b += t.chunk)
-                P.chunks.push_back(Chunk{r, s, b, std::min<int64_t>(b + t.chunk, R.cap[s])});
+                P.chunks.push_back(Chunk{r, s, b, std::min<int64_t>(b + t.chunk, R.cap[s]), R.poff[s]});
             R.nchunk[s] = (int32_t)P.chunks.size() - R.chunk0[s];
             for (int k = 0; k < R.ntiles[s]; ++k) {
                 int64_t b = (int64_t)k * t.sort_tile;
@@ -209,6 +209,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.hist = take(sizeof(int) * P.hist_entries);
     L.totals = take(sizeof(int64_t) * 2 * nruns);
     L.counts = take(sizeof(int2) * kMaxSpecies * kCountSlots * nruns);
+    L.push_err = take(sizeof(int) * nruns);
     L.inj = take(sizeof(InjectPlan) * nruns);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
@@ -277,9 +278,9 @@ void l_load(Context* c, hipStream_t s) {
 void l_push(Context* c, bool push, hipStream_t s) {
     const int per = c->P.tun.chunk / 64;
     if (prec(c) == SLPIC_F32)
-        launch_push_f32(push, per, c->a, (int)c->P.chunks.size(), 64, 0, s);
+        launch_push_f32(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, s);
     else
-        launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), 64, 0, s);
+        launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, s);
 }
 constexpr int kInjectGroups = 8;  // workgroups per run generating source particles
 void l_inject(Context* c, hipStream_t s) {
@@ -458,6 +459,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.hist = (int*)(w + L.hist);
     a.totals = (int64_t*)(w + L.totals);
     a.counts = (int2*)(w + L.counts);
+    a.push_err = (int*)(w + L.push_err);
     a.inj = (InjectPlan*)(w + L.inj);
     a.history = (double*)(w + L.history);
     c->btot = (long long*)(w + L.btot);

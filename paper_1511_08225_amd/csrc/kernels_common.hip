@@ -25,6 +25,7 @@ __global__ void k_init_state(KArgs a, int nruns) {
     st->pushed_total = 0;
     for (int j = 0; j < kMaxSpecies * kCountSlots; ++j)
         a.counts[(int64_t)r * kMaxSpecies * kCountSlots + j] = make_int2(0, 0);
+    a.push_err[r] = 0;
     st->acc_e = 0.0;
     st->phi_w = 0.0;
     st->error = 0;
@@ -36,8 +37,9 @@ __global__ void k_field(KArgs a, int advance) {
     field_solve(a, blockIdx.x, advance, D, D + a.runs[blockIdx.x].nodes);
 }
 
-// The step's field kernel: apply the source bookkeeping of the step to the
-// run state, clear the push counters, then solve for phi^{n+1}, E^{n+1}.
+// The step's field kernel: apply the source bookkeeping and the push error
+// flags of the step to the run state, clear the push counters, then solve
+// for phi^{n+1}, E^{n+1}.
 __global__ void k_field_step(KArgs a) {
     const int run = blockIdx.x;
     RunState* st = a.state + run;
@@ -51,6 +53,8 @@ __global__ void k_field_step(KArgs a) {
         st->pushed_total += ip.pushed;
         st->acc_e = ip.acc_e;
         if (ip.overflow) st->error |= 1;
+        st->error |= a.push_err[run];
+        a.push_err[run] = 0;
     }
     int2* cs = a.counts + (int64_t)run * kMaxSpecies * kCountSlots;
     for (int j = threadIdx.x; j < kMaxSpecies * kCountSlots; j += blockDim.x) cs[j] = make_int2(0, 0);

@@ -10,7 +10,7 @@ namespace slpic {
 #define SLPIC_DECLARE_LAUNCHERS(sfx)                                                                   \
     void launch_load_##sfx(const KArgs& a, int nchunks, int block, hipStream_t s);                     \
     void launch_push_##sfx(bool push, int per_thread, const KArgs& a, int nchunks, int block,          \
-                           size_t lds, hipStream_t s);                                                 \
+                           hipStream_t s);                                                             \
     void launch_velocity_map_##sfx(int beta_kind, double u, double dt, int64_t n, const void* vx,      \
                                    const void* c2, const void* acc, void* out, int* iters,             \
                                    hipStream_t s);                                                     \

@@ -63,10 +63,12 @@ struct InjectPlan {
     int32_t pad;
 };
 
-// A contiguous slot range of one (run, species): one push / load / moments workgroup.
+// A contiguous slot range of one (run, species): one push / load / moments
+// workgroup.  begin/end count from the (run, species) first slot, base.
 struct Chunk {
     int32_t run, species;
     int64_t begin, end;
+    int64_t base;
 };
 
 // Particle SoA buffers (double-buffered for the sort); positions are int32
@@ -101,6 +103,7 @@ struct KArgs {
     int* hist;            // sort histogram, per (run, species) at hoff
     int64_t* totals;      // live slots after the sort [run][species]
     int2* counts;         // [run][species][kCountSlots]: (absorbed, pushed) of the last push
+    int* push_err;        // [run]: error flags raised by the last push
     struct InjectPlan* inj;  // [run]: source counts of the current step
     int32_t* perm;        // last sort's permutation (new slot -> old slot)
 };
