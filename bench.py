@@ -52,6 +52,73 @@ def cpu_baseline(cfg: dict, budget_s: float = 12.0) -> dict:
                       f"FP64 C oracle, one thread"}
 
 
+def traffic_probe(args) -> int:
+    """The workload for the HBM traffic counters: a 1 GiB device copy (the
+    calibration kernel, 1 GiB read + 1 GiB written), then direct-launch steps
+    of the benchmark workload, so that every push dispatch is counted."""
+    import torch
+    import workloads
+    from paper_1511_08225_amd import slpic
+    src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc, sort_every=args.sort_every)
+    sim = slpic.Sim(cfg, precision=args.precision, sort_every=args.sort_every, chunk=args.chunk, graph_steps=0)
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "traffic", "steps": args.steps, "pushed": sim.pushed_total()}), flush=True)
+    sim.close()
+    return 0
+
+
+def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int) -> int:
+    """Per-launch HBM bytes of the push from two rocprofv3 --pmc counter files
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
+    counter reads for the 1 GiB copy; written where the benchmark reads it."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        push = [float(r["Counter_Value"]) for r in rows if "k_push_deposit" in r["Kernel_Name"]
+                and ", true," in r["Kernel_Name"]]
+        return copy, push
+
+    fc, fp = per_kernel(fetch_csv, "FETCH_SIZE")
+    wc, wp = per_kernel(write_csv, "WRITE_SIZE")
+    if not (fc and fp and wc and wp):
+        print("counter files lack the copy or push dispatches", file=sys.stderr)
+        return 1
+    gib_kib = 1024.0 * 1024.0
+    f_scale = gib_kib / max(fc)  # KiB actually read by the copy / KiB the counter reports
+    w_scale = gib_kib / max(wc)
+    fetch = sum(fp) / len(fp) * f_scale * 1024.0
+    write = sum(wp) / len(wp) * w_scale * 1024.0
+    out = {"workload": "production_sheath", "ppc": ppc, "chunk": chunk, "launches": len(fp),
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale,
+           "copy_fetch_kib": max(fc), "copy_write_kib": max(wc)}
+    table = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
+    table[str(ppc)] = out
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
+def traffic_for(ppc: int, chunk: int):
+    """Counter-measured HBM bytes per push launch, if recorded for this shape."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE)).get(str(ppc))
+    if t and t.get("workload") == "production_sheath" and t.get("chunk") == chunk:
+        return t.get("bytes_per_launch")
+    return None
+
+
 def run_timed(cfg, args, steps, warmup):
     import torch
     from paper_1511_08225_amd import slpic
@@ -86,7 +153,15 @@ def main() -> int:
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-variant", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the counter workload (copy calibration + direct-launch steps) and exit")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 counter files into the per-launch traffic record and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        return traffic_from(args.traffic_from[0], args.traffic_from[1], args.ppc, args.chunk)
+    if args.traffic_probe:
+        return traffic_probe(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
@@ -102,11 +177,7 @@ def main() -> int:
     push_ms = prof["ms"] / launches
     bytes_per_launch = bpp * pushes / launches
     achieved = bytes_per_launch / (push_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        t = json.load(open(TRAFFIC_FILE))
-        if t.get("workload") == "production_sheath" and t.get("chunk") == args.chunk:
-            traffic = t.get("bytes_per_launch")
+    traffic = traffic_for(args.ppc, args.chunk)
     line = {
         "metric": METRIC,
         "value": pushes / elapsed,
@@ -153,7 +224,8 @@ def main() -> int:
         a10 = bpp * p10 / l10 / (ms10 * 1e-3) / 1e9
         line["hbm_variant"] = {"particles": 2 * 2048 * 10 * args.ppc, "value": p10 / e10,
                                "push_avg_launch_ms": ms10, "achieved_GBs": a10,
-                               "frac": a10 / HBM_PEAK_GBS}
+                               "frac": a10 / HBM_PEAK_GBS,
+                               "traffic": traffic_for(10 * args.ppc, args.chunk)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -86,8 +86,11 @@ typedef struct {
     slpic_species species[2];
     uint64_t seed;         /* Philox key                                         */
     int32_t run_id;        /* enters the Philox counter                          */
-    int32_t reserved;
+    int32_t steady_window; /* steps per wall-potential window; 0 = max(1, nx/4)  */
     double capacity_factor;/* particle slots per species = ceil(cf * nx * ppc)  */
+    double steady_tol;     /* steady when the last three window means of Phi_w  */
+                           /* lie within steady_tol * |their mean| of it;       */
+                           /* 0 = default 0.02                                  */
 } slpic_run_config;
 
 typedef struct {
@@ -113,6 +116,10 @@ typedef struct {
     int32_t error_flags;       /* SLPIC_FLAG_* bits (sticky)                       */
     int32_t fixed_bits;        /* F32: fraction bits of the position fixed point   */
     double weight[2];          /* macroparticle weight per species, dx Z / ppc     */
+    int64_t steady_step;       /* step count when the run became steady, -1 before */
+    int64_t windows;           /* closed wall-potential windows                    */
+    double window_mean[3];     /* the last three window means of Phi_w, newest first */
+    int64_t moment_samples;    /* samples in the moment window (slpic_moments_sample) */
 } slpic_run_status;
 
 /* Bytes of device workspace needed for nruns runs (a sheath each) with the
@@ -139,6 +146,17 @@ int slpic_step(void* ctx, int32_t nsteps, void* stream);
  * the density n, the flux Gamma_x = n <v_x> and the kinetic-energy density.
  * Async on stream. */
 int slpic_moments(void* ctx, int32_t run, double* d_out, void* stream);
+
+/* Add the current moments of one run (run >= 0) or of every run (run = -1)
+ * to the run's moment window on the device: the raw beta-weighted sums of
+ * slpic_moments and phi, and one sample count.  Async; graph-free (call it
+ * between slpic_step calls at the cadence wanted). */
+int slpic_moments_sample(void* ctx, int32_t run, void* stream);
+
+/* The window mean of one run's moment samples, in the layout of
+ * slpic_moments (all zero without samples), to the caller's device buffer;
+ * reset != 0 then empties the window.  Async on stream. */
+int slpic_moments_window(void* ctx, int32_t run, double* d_out, int32_t reset, void* stream);
 
 /* Sync.  Copies the status of runs [0, nruns) to h_out. */
 int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns);

@@ -50,7 +50,18 @@ class _Config(ctypes.Structure):
                 ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run", ctypes.c_int32),
                 ("sort_every", ctypes.c_int32), ("sort_bucket", ctypes.c_int32),
                 ("kick", ctypes.c_int32), ("mmp_tol", ctypes.c_double),
-                ("capacity_factor", ctypes.c_double)]
+                ("capacity_factor", ctypes.c_double), ("steady_window", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("steady_tol", ctypes.c_double)]
+
+
+class _Steady(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("nopen", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("sum", ctypes.c_double), ("mean", ctypes.c_double * 3), ("nwin", ctypes.c_int64),
+                ("steady_step", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {"window": self.window, "steady_step": self.steady_step, "windows": self.nwin,
+                "window_mean": list(self.mean)}
 
 
 _lib = None
@@ -101,6 +112,9 @@ def lib():
             "orc_set_particles": (_I32, [_VP, _I32, _I64, _PD, _PD, _PD, _PD]),
             "orc_set_counters": (None, [_VP, _I64, _D]),
             "orc_get_grid": (None, [_VP, _PD, _PD, _PD, _PD]),
+            "orc_get_steady": (None, [_VP, ctypes.POINTER(_Steady)]),
+            "orc_steady_init": (None, [ctypes.POINTER(_Steady), ctypes.c_int32, _D]),
+            "orc_steady_feed": (None, [ctypes.POINTER(_Steady), _D, _I64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -143,7 +157,19 @@ def make_config(cfg: dict) -> _Config:
     c.kick = {"exact": KICK_EXACT, "mmp": KICK_MMP}[cfg.get("kick", "exact")]
     c.mmp_tol = float(cfg.get("mmp_tol", 0.01))
     c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
+    c.steady_window = int(cfg.get("steady_window", 0))
+    c.steady_tol = float(cfg.get("steady_tol", 0.0))
     return c
+
+
+def steady_detect(series, window: int, tol: float) -> dict:
+    """Run the wall-potential steady detector over a series (element k is
+    Phi_w after step k + 1)."""
+    d = _Steady()
+    lib().orc_steady_init(ctypes.byref(d), int(window), float(tol))
+    for k, v in enumerate(series):
+        lib().orc_steady_feed(ctypes.byref(d), float(v), k + 1)
+    return d.as_dict()
 
 
 # ---------------------------------------------------------------- primitives
@@ -308,6 +334,12 @@ class Run:
     def wall_potential(self) -> float:
         g = self.grid()
         return float(g["phi"][0] - g["phi"][-1])
+
+    def steady(self) -> dict:
+        """The wall-potential steady detector of this run."""
+        d = _Steady()
+        lib().orc_get_steady(self._h, ctypes.byref(d))
+        return d.as_dict()
 
     def weights(self):
         return [weight(self.cfg, s) for s in range(self.nspecies)]

@@ -454,7 +454,38 @@ void orc_poisson1d(int32_t nx, double dx, const double* Q, double* phi, double* 
 /* ------------------------------------------------------------------------ */
 /* A run: particle slots (dead slots have xt < 0 until compaction), grids.   */
 /* ------------------------------------------------------------------------ */
+/* ---------------------------------------------------------------- steady */
+void orc_steady_init(orc_steady* d, int32_t window, double tol) {
+    memset(d, 0, sizeof *d);
+    d->window = window;
+    d->tol = tol;
+    d->steady_step = -1;
+}
+
+void orc_steady_feed(orc_steady* d, double phi_w, int64_t step_count) {
+    d->sum += phi_w;
+    d->nopen += 1;
+    if (d->nopen < d->window) return;
+    double m = d->sum / (double)d->window;
+    d->mean[2] = d->mean[1];
+    d->mean[1] = d->mean[0];
+    d->mean[0] = m;
+    d->nwin += 1;
+    d->sum = 0.0;
+    d->nopen = 0;
+    if (d->nwin >= 3 && d->steady_step < 0) {
+        double avg = (d->mean[0] + d->mean[1] + d->mean[2]) / 3.0;
+        double dev = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double e = fabs(d->mean[k] - avg);
+            if (e > dev) dev = e;
+        }
+        if (dev <= d->tol * fabs(avg)) d->steady_step = step_count;
+    }
+}
+
 struct orc_run {
+    orc_steady steady;
     orc_config cfg;
     double w[2], qw[2], qm[2], vt[2];
     int64_t n[2], cap[2];
@@ -479,6 +510,8 @@ static void ensure_capacity(orc_run* r, int s, int64_t need) {
 orc_run* orc_create(const orc_config* cfg) {
     orc_run* r = (orc_run*)calloc(1, sizeof(orc_run));
     r->cfg = *cfg;
+    orc_steady_init(&r->steady, cfg->steady_window > 0 ? cfg->steady_window : (cfg->nx / 4 > 1 ? cfg->nx / 4 : 1),
+                    cfg->steady_tol > 0.0 ? cfg->steady_tol : 0.02);
     int nodes = cfg->nx + 1;
     for (int s = 0; s < cfg->nspecies; ++s) {
         r->vt[s] = species_vt(cfg, s);
@@ -663,6 +696,7 @@ void orc_step(orc_run* r, int32_t nsteps) {
         deposit(r);
         solve_fields(r);
         r->step += 1;
+        orc_steady_feed(&r->steady, r->phi[0] - r->phi[cfg->nx], r->step);
         if (cfg->sort_every > 0 && r->step % cfg->sort_every == 0) orc_sort(r, NULL, NULL);
     }
 }
@@ -743,3 +777,5 @@ void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double*
     if (phi) memcpy(phi, r->phi, nodes * sizeof(double));
     if (E) memcpy(E, r->E, nodes * sizeof(double));
 }
+
+void orc_get_steady(const orc_run* r, orc_steady* out) { *out = r->steady; }

@@ -52,7 +52,29 @@ typedef struct {
     int32_t kick;          /* ORC_KICK_EXACT / ORC_KICK_MMP                  */
     double mmp_tol;        /* relative tolerance of the modified midpoint    */
     double capacity_factor;
+    int32_t steady_window; /* steps per wall-potential window; 0: max(1, nx/4) */
+    int32_t pad;
+    double steady_tol;     /* relative spread of three window means; 0: 0.02 */
 } orc_config;
+
+/* Steady-state detector on the wall potential (a reading: the paper calls
+ * the late state an equilibrium without a test).  Steps are grouped into
+ * windows of W steps; each closed window's mean joins the last three, and
+ * the run is steady at the first step count where the largest deviation of
+ * those three means from their average is at most tol * |average|. */
+typedef struct {
+    int32_t window;        /* W */
+    int32_t nopen;         /* steps in the open window */
+    double tol;
+    double sum;            /* sum of Phi_w over the open window */
+    double mean[3];        /* last three window means, newest first */
+    int64_t nwin;          /* closed windows */
+    int64_t steady_step;   /* step count when first steady, -1 before */
+} orc_steady;
+
+void orc_steady_init(orc_steady* d, int32_t window, double tol);
+/* Feed the wall potential after a step; step_count = steps completed. */
+void orc_steady_feed(orc_steady* d, double phi_w, int64_t step_count);
 
 typedef struct orc_run orc_run;
 
@@ -100,6 +122,7 @@ int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const d
                       const double* vy, const double* vz);
 void orc_set_counters(orc_run* r, int64_t step, double acc_e);
 void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E);
+void orc_get_steady(const orc_run* r, orc_steady* out);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
-        totals, counts, push_err, inj, btot, history, total;
+        totals, counts, push_err, Macc, inj, btot, history, total;
 };
 
 struct Plan {
@@ -151,6 +151,9 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             hoff += (int64_t)R.nkeys * R.ntiles[s];
         }
         R.inj_ratio = R.w[1] / R.w[0];
+        if (c.steady_window < 0 || !(c.steady_tol >= 0.0)) return SLPIC_EINVAL;
+        R.steady_window = c.steady_window > 0 ? c.steady_window : std::max(1, c.nx / 4);
+        R.steady_tol = c.steady_tol > 0.0 ? c.steady_tol : 0.02;
         R.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
         R.seed_hi = (uint32_t)(c.seed >> 32);
         R.run_id = (uint32_t)c.run_id;
@@ -210,6 +213,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.totals = take(sizeof(int64_t) * 2 * nruns);
     L.counts = take(sizeof(int2) * kMaxSpecies * kCountSlots * nruns);
     L.push_err = take(sizeof(int) * nruns);
+    L.Macc = take(sizeof(double) * 7 * P.total_nodes);
     L.inj = take(sizeof(InjectPlan) * nruns);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
@@ -460,6 +464,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.totals = (int64_t*)(w + L.totals);
     a.counts = (int2*)(w + L.counts);
     a.push_err = (int*)(w + L.push_err);
+    a.Macc = (double*)(w + L.Macc);
     a.inj = (InjectPlan*)(w + L.inj);
     a.history = (double*)(w + L.history);
     c->btot = (long long*)(w + L.btot);
@@ -489,6 +494,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     launch_init_state(a, nruns, s);
     launch_zero(a.Qacc, 2 * c->P.total_nodes, s);
+    launch_zero(a.Macc, 7 * c->P.total_nodes, s);
     launch_zero(a.Qlast, 2 * c->P.total_nodes, s);
     launch_zero(a.E, c->P.total_nodes, s);
     launch_zero(a.phi, c->P.total_nodes, s);
@@ -547,10 +553,32 @@ int slpic_moments(void* ctx, int32_t run, double* d_out, void* stream) {
     const RunInfo& R = c->P.runs[run];
     launch_zero(d_out, (int64_t)7 * R.nodes, s);
     if (prec(c) == SLPIC_F32)
-        launch_moments_f32(c->a, c->P.run_chunk0[run], c->P.run_nchunks[run], 256, c->moments_lds, d_out, s);
+        launch_moments_f32(c->a, c->P.run_chunk0[run], c->P.run_nchunks[run], 256, c->moments_lds, d_out, 0, s);
     else
-        launch_moments_f64(c->a, c->P.run_chunk0[run], c->P.run_nchunks[run], 256, c->moments_lds, d_out, s);
+        launch_moments_f64(c->a, c->P.run_chunk0[run], c->P.run_nchunks[run], 256, c->moments_lds, d_out, 0, s);
     launch_moments_finish(c->a, run, d_out, s);
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+}
+
+int slpic_moments_sample(void* ctx, int32_t run, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c || run < -1 || run >= c->P.nruns) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int r0 = run < 0 ? 0 : run, nr = run < 0 ? c->P.nruns : 1;
+    const int ch0 = c->P.run_chunk0[r0];
+    const int nch = run < 0 ? (int)c->P.chunks.size() : c->P.run_nchunks[run];
+    if (prec(c) == SLPIC_F32)
+        launch_moments_f32(c->a, ch0, nch, 256, c->moments_lds, c->a.Macc, 1, s);
+    else
+        launch_moments_f64(c->a, ch0, nch, 256, c->moments_lds, c->a.Macc, 1, s);
+    launch_moments_sample_finish(c->a, r0, nr, s);
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+}
+
+int slpic_moments_window(void* ctx, int32_t run, double* d_out, int32_t reset, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c || !d_out || run < 0 || run >= c->P.nruns) return SLPIC_EINVAL;
+    launch_moments_window(c->a, run, d_out, reset != 0, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
 }
 
@@ -576,6 +604,10 @@ int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns) {
         o.wall_potential = st[r].phi_w;
         o.error_flags = st[r].error;
         o.fixed_bits = c->P.tun.precision == SLPIC_F32 ? R.fb : 0;
+        o.steady_step = st[r].steady_step;
+        o.windows = st[r].nwin;
+        for (int k = 0; k < 3; ++k) o.window_mean[k] = st[r].win_mean[k];
+        o.moment_samples = st[r].msamples;
     }
     return SLPIC_OK;
 }

@@ -29,9 +29,15 @@ __global__ void k_init_state(KArgs a, int nruns) {
     st->acc_e = 0.0;
     st->phi_w = 0.0;
     st->error = 0;
+    st->win_n = 0;
+    st->win_sum = 0.0;
+    for (int k = 0; k < 3; ++k) st->win_mean[k] = 0.0;
+    st->nwin = 0;
+    st->steady_step = -1;
+    st->msamples = 0;
 }
 
-__global__ void k_field(KArgs a, int advance) {
+__global__ __launch_bounds__(kFieldThreads) void k_field(KArgs a, int advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* D = (double*)smem;
     field_solve(a, blockIdx.x, advance, D, D + a.runs[blockIdx.x].nodes);
@@ -40,7 +46,7 @@ __global__ void k_field(KArgs a, int advance) {
 // The step's field kernel: apply the source bookkeeping and the push error
 // flags of the step to the run state, clear the push counters, then solve
 // for phi^{n+1}, E^{n+1}.
-__global__ void k_field_step(KArgs a) {
+__global__ __launch_bounds__(kFieldThreads) void k_field_step(KArgs a) {
     const int run = blockIdx.x;
     RunState* st = a.state + run;
     if (threadIdx.x == 0) {
@@ -58,7 +64,6 @@ __global__ void k_field_step(KArgs a) {
     }
     int2* cs = a.counts + (int64_t)run * kMaxSpecies * kCountSlots;
     for (int j = threadIdx.x; j < kMaxSpecies * kCountSlots; j += blockDim.x) cs[j] = make_int2(0, 0);
-    __syncthreads();
     extern __shared__ __align__(16) unsigned char smem[];
     double* D = (double*)smem;
     field_solve(a, run, 1, D, D + a.runs[run].nodes);
@@ -133,6 +138,39 @@ __global__ void k_zero(double* p, int64_t n) {
 }
 
 // Moments: potential into row 0, accumulated sums divided by the node volume.
+// Window means of the moment samples of one run (phi, then per species n,
+// Gamma_x, energy density, each node's sums over dV), optionally clearing
+// the window afterwards.  One workgroup.
+__global__ void k_moments_window(KArgs a, int run, double* out, int reset) {
+    const RunInfo& R = a.runs[run];
+    RunState* st = a.state + run;
+    const int nodes = R.nodes;
+    double* M = a.Macc + 7 * R.goff;
+    const int64_t ns = st->msamples;
+    const double inv = ns > 0 ? 1.0 / (double)ns : 0.0;
+    for (int j = threadIdx.x; j < nodes; j += blockDim.x) {
+        const double dV = (j == 0 || j == nodes - 1) ? 0.5 * R.dx : R.dx;
+        out[j] = M[j] * inv;
+        for (int r = 1; r < 7; ++r) out[(int64_t)r * nodes + j] = M[(int64_t)r * nodes + j] * inv / dV;
+    }
+    if (reset) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < 7 * nodes; j += blockDim.x) M[j] = 0.0;
+        if (threadIdx.x == 0) st->msamples = 0;
+    }
+}
+
+// After the raw moment sums of a sample were added to the accumulators: add
+// phi and count the sample.  One workgroup per run.
+__global__ void k_moments_sample_finish(KArgs a, int run0) {
+    const int run = run0 + blockIdx.x;
+    const RunInfo& R = a.runs[run];
+    double* M = a.Macc + 7 * R.goff;
+    const double* phi = a.phi + R.goff;
+    for (int j = threadIdx.x; j < R.nodes; j += blockDim.x) M[j] += phi[j];
+    if (threadIdx.x == 0) a.state[run].msamples += 1;
+}
+
 __global__ void k_moments_finish(KArgs a, int run, double* out) {
     const RunInfo& R = a.runs[run];
     const int nodes = R.nodes;
@@ -148,10 +186,10 @@ void launch_init_state(const KArgs& a, int nruns, hipStream_t s) {
     hipLaunchKernelGGL(k_init_state, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns);
 }
 void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_field, dim3(nruns), dim3(256), lds, s, a, advance);
+    hipLaunchKernelGGL(k_field, dim3(nruns), dim3(kFieldThreads), lds, s, a, advance);
 }
 void launch_field_step(const KArgs& a, int nruns, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_field_step, dim3(nruns), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_field_step, dim3(nruns), dim3(kFieldThreads), lds, s, a);
 }
 int scan_blocks(int64_t n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
 void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s) {
@@ -170,6 +208,12 @@ void launch_zero(double* p, int64_t n, hipStream_t s) {
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+void launch_moments_window(const KArgs& a, int run, double* out, int reset, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments_window, dim3(1), dim3(256), 0, s, a, run, out, reset);
+}
+void launch_moments_sample_finish(const KArgs& a, int run0, int nruns, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments_sample_finish, dim3(nruns), dim3(256), 0, s, a, run0);
 }
 void launch_moments_finish(const KArgs& a, int run, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_moments_finish, dim3(8), dim3(256), 0, s, a, run, out);

@@ -16,7 +16,7 @@ namespace slpic {
                                    hipStream_t s);                                                     \
     void launch_inject_##sfx(const KArgs& a, int nruns, int groups, size_t lds, hipStream_t s);         \
     void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \
-                              double* out, hipStream_t s);                                             \
+                              double* out, int per_run, hipStream_t s);                                \
     void launch_sort_hist_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);     \
     void launch_sort_scatter_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);
 
@@ -34,5 +34,7 @@ void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const l
                         hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);
 void launch_moments_finish(const KArgs& a, int run, double* out, hipStream_t s);
+void launch_moments_window(const KArgs& a, int run, double* out, int reset, hipStream_t s);
+void launch_moments_sample_finish(const KArgs& a, int run0, int nruns, hipStream_t s);
 
 }  // namespace slpic

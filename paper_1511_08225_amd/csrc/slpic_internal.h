@@ -35,6 +35,9 @@ struct RunInfo {
     int32_t ntiles[kMaxSpecies]; // sort tiles of (run, species)
     int32_t chunk0[kMaxSpecies]; // first push chunk of (run, species)
     int32_t nchunk[kMaxSpecies]; // push chunks of (run, species)
+    int32_t steady_window;       // steps per wall-potential window
+    int32_t pad1;
+    double steady_tol;           // relative spread of three window means that counts as steady
 };
 
 // Mutable per-run state, updated on the device.
@@ -48,7 +51,12 @@ struct alignas(64) RunState {
     double acc_e;
     double phi_w;
     int32_t error;
-    int32_t pad;
+    int32_t win_n;               // steps in the open wall-potential window
+    double win_sum;              // sum of phi_w over the open window
+    double win_mean[3];          // the last three closed window means, newest first
+    int64_t nwin;                // closed windows
+    int64_t steady_step;         // step count when first steady, -1 before
+    int64_t msamples;            // moment samples in the window accumulator
 };
 
 // Source bookkeeping of one step, computed from the push counters before the
@@ -106,6 +114,7 @@ struct KArgs {
     int* push_err;        // [run]: error flags raised by the last push
     struct InjectPlan* inj;  // [run]: source counts of the current step
     int32_t* perm;        // last sort's permutation (new slot -> old slot)
+    double* Macc;         // moment window accumulators [run]: 7 rows of nodes at 7*goff
 };
 
 }  // namespace slpic

@@ -38,7 +38,8 @@ class RunConfig(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("u", ctypes.c_double),
                 ("nspecies", ctypes.c_int32), ("source_cells", ctypes.c_int32),
                 ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run_id", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("capacity_factor", ctypes.c_double)]
+                ("steady_window", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
+                ("steady_tol", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -53,14 +54,18 @@ class RunStatus(ctypes.Structure):
                 ("capacity", ctypes.c_int64 * 2), ("absorbed_total", ctypes.c_int64 * 2),
                 ("injected_total", ctypes.c_int64 * 2), ("acc_e", ctypes.c_double),
                 ("wall_potential", ctypes.c_double), ("error_flags", ctypes.c_int32),
-                ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2)]
+                ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2),
+                ("steady_step", ctypes.c_int64), ("windows", ctypes.c_int64),
+                ("window_mean", ctypes.c_double * 3), ("moment_samples", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {"step": self.step, "nslots": list(self.nslots), "capacity": list(self.capacity),
                 "absorbed_total": list(self.absorbed_total),
                 "injected_total": list(self.injected_total), "acc_e": self.acc_e,
                 "wall_potential": self.wall_potential, "error_flags": self.error_flags,
-                "fixed_bits": self.fixed_bits, "weight": list(self.weight)}
+                "fixed_bits": self.fixed_bits, "weight": list(self.weight),
+                "steady_step": self.steady_step, "windows": self.windows,
+                "window_mean": list(self.window_mean), "moment_samples": self.moment_samples}
 
 
 _lib = None
@@ -84,6 +89,8 @@ def lib():
                                           ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
             "slpic_step": (ctypes.c_int, [_P, i32, _P]),
             "slpic_moments": (ctypes.c_int, [_P, i32, _P, _P]),
+            "slpic_moments_sample": (ctypes.c_int, [_P, i32, _P]),
+            "slpic_moments_window": (ctypes.c_int, [_P, i32, _P, i32, _P]),
             "slpic_status_query": (ctypes.c_int, [_P, ctypes.POINTER(RunStatus), i32]),
             "slpic_export_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, _PI64]),
             "slpic_import_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, i64]),
@@ -135,6 +142,8 @@ def run_config(cfg: dict) -> RunConfig:
     c.seed = int(cfg.get("seed", 0))
     c.run_id = int(cfg.get("run", 0))
     c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
+    c.steady_window = int(cfg.get("steady_window", 0))
+    c.steady_tol = float(cfg.get("steady_tol", 0.0))
     return c
 
 
@@ -248,6 +257,19 @@ class Sim:
         nodes = self.configs[run]["nx"] + 1
         out = torch.empty((7, nodes), dtype=torch.float64, device=self.device)
         _check(lib().slpic_moments(self._ctx, run, _P(out.data_ptr()), self._stream()), "slpic_moments")
+        return out
+
+    def moments_sample(self, run: int = -1):
+        """Add the current moments of one run (or all, run = -1) to the
+        device moment windows."""
+        _check(lib().slpic_moments_sample(self._ctx, int(run), self._stream()), "slpic_moments_sample")
+
+    def moments_window(self, run: int = 0, reset: bool = False) -> torch.Tensor:
+        """Window mean of the sampled moments of one run (layout of moments())."""
+        nodes = self.configs[run]["nx"] + 1
+        out = torch.empty((7, nodes), dtype=torch.float64, device=self.device)
+        _check(lib().slpic_moments_window(self._ctx, run, _P(out.data_ptr()), int(bool(reset)), self._stream()),
+               "slpic_moments_window")
         return out
 
     def wall_potential(self, run: int = 0) -> float:

@@ -111,6 +111,13 @@ def test_lockstep_every_step_small_sheath_f64(gpu_lib):
             st = sim.status(0)
             assert st["absorbed_total"] is not None
     print_case(f"lockstep worst rel charge error {worst:.3e}")
+    # the wall-potential windows and the steady step, fed by every step
+    st, od = sim.status(0), run.steady()
+    print_case(f"steady detector: gpu {st['steady_step']} oracle {od['steady_step']} windows {od['windows']}")
+    assert st["windows"] == od["windows"] == nsteps // (cfg["nx"] // 4)
+    for g, o in zip(st["window_mean"], od["window_mean"]):
+        assert g == pytest.approx(o, rel=1e-10, abs=1e-12)
+    assert st["steady_step"] == od["steady_step"]
 
 
 def test_unlimited_speed_reduces_to_pic_f64(gpu_lib):
@@ -223,6 +230,28 @@ def test_moments_match_oracle_f64(gpu_lib):
         assert rel_inf(mg[row], mo[row]) <= 1e-11, row
 
 
+def test_moment_window_matches_oracle_mean_f64(gpu_lib):
+    """Five moment samples at oracle states three steps apart: the device
+    window mean equals the mean of the oracle's moments; reset empties it."""
+    cfg = workloads.small_sheath(sort_every=0, seed=11)
+    run = oracle.Run(cfg)
+    run.step(30)
+    sim = gpu_lib.Sim(cfg, precision="f64", sort_every=0)
+    acc = None
+    for _ in range(5):
+        push_oracle_to_gpu(sim, 0, run, quantize=False)
+        sim.moments_sample(0)
+        mo = run.moments()
+        acc = mo if acc is None else acc + mo
+        run.step(3)
+    assert sim.status(0)["moment_samples"] == 5
+    mg = sim.moments_window(0, reset=True).cpu().numpy()
+    for row in range(7):
+        assert rel_inf(mg[row], acc[row] / 5) <= 1e-11, row
+    assert sim.status(0)["moment_samples"] == 0
+    assert not sim.moments_window(0).abs().max().item()
+
+
 def test_batched_runs_match_their_oracles(gpu_lib):
     """Ragged runs in one context (different cells, ppc, ion mass, speed
     limit) each match their own oracle after one step."""
@@ -240,6 +269,13 @@ def test_batched_runs_match_their_oracles(gpu_lib):
     for r, run in enumerate(runs):
         run.step(1)
         _compare_step(sim, run, r=r)
+    # one moment sample of every run at once
+    sim.moments_sample(-1)
+    for r, run in enumerate(runs):
+        mg = sim.moments_window(r).cpu().numpy()
+        mo = run.moments()
+        for row in range(7):
+            assert rel_inf(mg[row], mo[row]) <= 1e-11, (r, row)
 
 
 def test_graph_replay_matches_direct_launches(gpu_lib):

@@ -533,3 +533,59 @@ def test_one_step_against_independent_particle_ode():
             assert xo[i] == pytest.approx(xn, rel=1e-9, abs=1e-9)
             assert vxo[i] == pytest.approx(v1[0], rel=2e-7, abs=1e-9)
             assert vyo[i] == vy[i] and vzo[i] == vz[i]
+
+
+# ---------------------------------------------------------------- steady detector
+def test_steady_detector_constant_series():
+    """A constant wall potential is steady when the third window closes."""
+    for W in (1, 4, 16):
+        d = oracle.steady_detect([3.25] * (5 * W), W, 0.02)
+        assert d["steady_step"] == 3 * W
+        assert d["windows"] == 5
+        assert d["window_mean"] == [3.25, 3.25, 3.25]
+
+
+def test_steady_detector_linear_ramp():
+    """Phi_k = a + b k (k = 1, 2, ...): window j (steps (j-1)W+1 .. jW) has
+    mean a + b((j-1)W + (W+1)/2); three consecutive means deviate from their
+    average by at most |b| W, so the run is steady at the first j >= 3 with
+    |b| W <= tol |a + b((j-2)W + (W+1)/2)|, at step jW."""
+    a, b, W, tol = 2.0, 0.01, 8, 0.02
+    n = 4000
+    series = [a + b * k for k in range(1, n + 1)]
+    d = oracle.steady_detect(series, W, tol)
+    j = 3
+    while not abs(b) * W <= tol * abs(a + b * ((j - 2) * W + (W + 1) / 2)):
+        j += 1
+    assert d["steady_step"] == j * W
+    # the window means themselves (closed form)
+    jl = n // W
+    for k, m in enumerate(d["window_mean"]):
+        assert m == pytest.approx(a + b * ((jl - 1 - k) * W + (W + 1) / 2), rel=1e-13)
+
+
+def test_steady_detector_step_change():
+    """A relaxing series that is flat (Phi = 1) from step K0 + 1 on, with
+    Phi_k = 2 + K0 - k >= 2 before: a window holding any step <= K0 has a mean
+    of at least 1 + 1/W, far outside 2 % of the flat windows, so the run is
+    steady once all three windows lie after K0, at step (3 + ceil(K0/W)) W."""
+    W, K0 = 10, 37
+    series = [2.0 + K0 - k if k <= K0 else 1.0 for k in range(1, 200)]
+    d = oracle.steady_detect(series, W, 0.02)
+    assert d["steady_step"] == (3 + math.ceil(K0 / W)) * W
+
+
+def test_steady_detector_matches_run_history():
+    """The detector inside a run sees the run's own wall potential after each
+    step (defaults: W = nx/4, tol = 0.02)."""
+    cfg = workloads.small_sheath(sort_every=1)
+    run = oracle.Run(cfg)
+    series = []
+    for _ in range(200):
+        run.step(1)
+        series.append(run.wall_potential())
+    d = oracle.steady_detect(series, cfg["nx"] // 4, 0.02)
+    got = run.steady()
+    assert got["steady_step"] == d["steady_step"]
+    assert got["windows"] == d["windows"] == 200 // (cfg["nx"] // 4)
+    assert got["window_mean"] == d["window_mean"]
