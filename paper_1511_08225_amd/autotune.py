@@ -1,0 +1,109 @@
+"""Launch-parameter tuner for a set of runs.
+
+Chooses the push chunk (particles per wavefront), the push workgroup size,
+the sort period and the sort key bucket for a given run set by timing short
+trials of the real step on the GPU (coordinate descent over the candidate
+lists), and caches the choice per workload signature in a JSON file so that
+later contexts over similar run sets start tuned.  The sort schedule changes
+only the slot order (the physics is the same up to FP64 summation order), so
+every candidate is a valid setting.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+from . import slpic
+
+CANDIDATES = {
+    "chunk": (256, 512),
+    "block": (64, 128, 256),
+    "sort_every": (8, 16, 32, 64),
+    "sort_bucket": (1, 2, 4),
+}
+DEFAULT = {"chunk": 512, "block": 128, "sort_every": 16, "sort_bucket": 1}
+CACHE_PATH = os.environ.get("SLPIC_TUNING_CACHE",
+                            os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json"))
+
+
+def signature(configs: list[dict], precision: str) -> str:
+    """Workload key: precision, run count, total particles and mean cells
+    (each rounded to a power of two), mean speed limit in ion thermal speeds
+    (rounded to an integer)."""
+    n = len(configs)
+    parts = sum(c["nx"] * sum(s["ppc"] for s in c["species"]) for c in configs)
+    cells = sum(c["nx"] for c in configs) / n
+    k = sum(c.get("u_over_vti", 0.0) if math.isfinite(c.get("u_over_vti", math.inf)) else 0.0
+            for c in configs) / n
+    return (f"{precision}|runs={1 << max(0, round(math.log2(n)))}|particles=2^{round(math.log2(max(parts, 1)))}"
+            f"|cells={1 << round(math.log2(max(cells, 1)))}|u={round(k)}")
+
+
+def _load_cache(path: str) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, warmup: int = 32) -> float:
+    """Seconds per particle-step of the whole step (push, source, field,
+    amortised sort) with these parameters, over `steps` graph-replayed steps
+    after `warmup` steps from the cold load."""
+    se = params["sort_every"]
+    g = max(16, se)
+    steps = max(g, (steps // g) * g)
+    warmup = max(g, (warmup // g) * g)
+    sim = slpic.Sim(configs, precision=precision, sort_every=se, sort_bucket=params["sort_bucket"],
+                    chunk=params["chunk"], block=params["block"], graph_steps=g)
+    try:
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        p0 = sim.pushed_total()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pushes = sim.pushed_total() - p0
+    finally:
+        sim.close()
+    return dt / max(pushes, 1)
+
+
+def tune(configs: list[dict], precision: str = "f32", cache_path: str = CACHE_PATH, force: bool = False,
+         steps: int = 64, warmup: int = 32, log=None, measure_fn=None) -> dict:
+    """Best parameters for this run set (cached by signature).  measure_fn
+    (configs, precision, params, steps, warmup) -> seconds per particle-step
+    defaults to timing the real step on the GPU."""
+    measure_fn = measure_fn or measure
+    key = signature(configs, precision)
+    cache = _load_cache(cache_path)
+    if not force and key in cache:
+        return dict(cache[key]["params"])
+    best = dict(DEFAULT)
+    best_t = measure_fn(configs, precision, best, steps, warmup)
+    trials = [(dict(best), best_t)]
+    for group in (("chunk", "block"), ("sort_every",), ("sort_bucket",)):
+        options = [{}]
+        for name in group:
+            options = [dict(o, **{name: v}) for o in options for v in CANDIDATES[name]]
+        for opt in options:
+            p = dict(best, **opt)
+            if any(p == q for q, _ in trials):  # measured already
+                continue
+            t = measure_fn(configs, precision, p, steps, warmup)
+            trials.append((dict(p), t))
+            if log:
+                log(f"trial {p}: {t * 1e12:.2f} ps/push")
+            if t < best_t:
+                best, best_t = p, t
+    cache[key] = {"params": best, "ps_per_push": best_t * 1e12,
+                  "trials": [{"params": p, "ps_per_push": t * 1e12} for p, t in trials]}
+    os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+    with open(cache_path, "w") as f:
+        json.dump(cache, f, indent=1)
+    return dict(best)

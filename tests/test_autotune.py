@@ -1,0 +1,53 @@
+"""The launch-parameter tuner: signature, coordinate descent and cache (CPU,
+with a synthetic cost), and one real tuning pass on the GPU."""
+import json
+
+import pytest
+
+import workloads
+from paper_1511_08225_amd import autotune
+
+
+def _cost(optimum):
+    """A separable cost with its minimum at `optimum` (seconds per push)."""
+    def f(configs, precision, params, steps, warmup):
+        return 1e-11 * (1.0 + sum(abs(autotune.CANDIDATES[k].index(params[k]) -
+                                      autotune.CANDIDATES[k].index(optimum[k])) for k in optimum))
+    return f
+
+
+def test_signature_groups_similar_run_sets():
+    a = workloads.batched_sweep(nruns=16, seed=1)
+    b = workloads.batched_sweep(nruns=16, seed=2)
+    assert autotune.signature(a, "f32") != autotune.signature(a, "f64")
+    assert autotune.signature(a, "f32").startswith("f32|runs=16|")
+    assert autotune.signature(a[:1], "f32") != autotune.signature(a, "f32")
+    # same distribution, same size class: usually the same key
+    assert autotune.signature(a, "f32").split("|")[1] == autotune.signature(b, "f32").split("|")[1]
+
+
+def test_coordinate_descent_finds_separable_optimum_and_caches(tmp_path):
+    cfgs = workloads.batched_sweep(nruns=4, seed=3, cells_range=(64, 128), ppc_range=(20, 40))
+    opt = {"chunk": 256, "block": 256, "sort_every": 32, "sort_bucket": 2}
+    path = str(tmp_path / "cache.json")
+    got = autotune.tune(cfgs, "f32", cache_path=path, measure_fn=_cost(opt))
+    assert got == opt
+    cache = json.load(open(path))
+    key = autotune.signature(cfgs, "f32")
+    assert cache[key]["params"] == opt
+    assert len(cache[key]["trials"]) == 1 + (2 * 3 - 1) + (4 - 1) + (3 - 1)
+    # a cached key is returned without measuring
+    def boom(*a):
+        raise AssertionError("measured a cached signature")
+    assert autotune.tune(cfgs, "f32", cache_path=path, measure_fn=boom) == opt
+
+
+@pytest.mark.gpu
+def test_tune_real_step_small_batch(gpu_lib, tmp_path):
+    cfgs = workloads.batched_sweep(nruns=8, seed=4, cells_range=(128, 256), ppc_range=(100, 200))
+    path = str(tmp_path / "cache.json")
+    got = autotune.tune(cfgs, "f32", cache_path=path, steps=32, warmup=16)
+    for k, v in got.items():
+        assert v in autotune.CANDIDATES[k]
+    rec = json.load(open(path))[autotune.signature(cfgs, "f32")]
+    assert rec["ps_per_push"] == min(t["ps_per_push"] for t in rec["trials"])

@@ -35,7 +35,8 @@ def ion_thermal_speed(te_over_ti: float, ion_amu: float) -> float:
 def sheath(nx: int, ppc: int, u_over_vti: float, dt: float | None = None, te_over_ti: float = 20.0,
            ion_amu: float = 40.0, dx: float = 0.5, seed: int = 0, run: int = 0,
            beta_kind: str = "step", sort_every: int = 1, sort_bucket: int = 1,
-           capacity_factor: float = 1.5, source_cells: int = 4) -> dict:
+           capacity_factor: float = 1.5, source_cells: int = 4, steady_window: int = 0,
+           steady_tol: float = 0.0) -> dict:
     """A 1D3V sheath: symmetry plane at x = 0, grounded absorbing wall at
     x = nx*dx, thermal source in the first ``source_cells`` cells.
 
@@ -56,6 +57,7 @@ def sheath(nx: int, ppc: int, u_over_vti: float, dt: float | None = None, te_ove
         "seed": int(seed), "run": int(run), "sort_every": int(sort_every),
         "sort_bucket": int(sort_bucket), "capacity_factor": float(capacity_factor),
         "te_over_ti": float(te_over_ti), "ion_amu": float(ion_amu), "u_over_vti": float(u_over_vti),
+        "steady_window": int(steady_window), "steady_tol": float(steady_tol),
     }
 
 
