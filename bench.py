@@ -119,6 +119,111 @@ def traffic_for(ppc: int, chunk: int):
     return None
 
 
+def sweep_bench(args) -> int:
+    """The batched sweep: 256 independent sheaths (ragged cells and particle
+    counts) advanced together, launch parameters from the autotuner; prints
+    one JSON line with pushes/s over the whole step."""
+    import torch
+    import workloads
+    from paper_1511_08225_amd import autotune, slpic
+    cfgs = workloads.batched_sweep(nruns=args.runs, seed=1)
+    t0 = time.perf_counter()
+    params = autotune.tune(cfgs, args.precision, log=lambda m: print(m, file=sys.stderr, flush=True))
+    tune_s = time.perf_counter() - t0
+    g = max(16, params["sort_every"])
+    sim = slpic.Sim(cfgs, precision=args.precision, sort_every=params["sort_every"],
+                    sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"], graph_steps=g)
+    steps = max(g, (args.steps // g) * g)
+    sim.step(g * max(1, args.warmup // g))
+    torch.cuda.synchronize()
+    sim.profile(True)
+    p0 = sim.pushed_total()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    pushes = sim.pushed_total() - p0
+    prof = sim.profile_read()["push"]
+    st = sim.status()
+    sim.close()
+    npart = sum(c["nx"] * 2 * c["species"][0]["ppc"] for c in cfgs)
+    push_ms = prof["ms"] / max(prof["launches"], 1)
+    achieved = BYTES_PER_PUSH[args.precision] * pushes / max(prof["launches"], 1) / (push_ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "particle-pushes/s (batched sweep)", "value": pushes / el, "unit": "particle-pushes/s",
+        "n_gpus": 1, "steps": steps, "ms_per_step": el * 1e3 / steps, "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{args.runs} independent 1D3V sheaths: cells U[128, 2048], ppc U[200, 1000], "
+                               f"Te/Ti log-U[5, 100], ion mass {{4, 20, 40, 84}} amu, u U[2, 10] v_ti",
+                   "runs": args.runs, "particles_at_load": npart, "tuned": params, "tune_seconds": tune_s},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_push_deposit", "avg_launch_ms": push_ms},
+        "error_flags": sum(1 for s in st if s["error_flags"]),
+    }), flush=True)
+    return 0
+
+
+def _to_steady(sim, nruns, max_steps, block):
+    """Step until every run is steady (or max_steps); returns per-run steady
+    steps (-1 if not reached), per-run wall seconds when first seen steady
+    (block granularity), total wall seconds and steps taken."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seen = [None] * nruns
+    steps = 0
+    st = sim.status()
+    while steps < max_steps:
+        sim.step(block)
+        steps += block
+        st = sim.status()  # synchronises
+        now = time.perf_counter() - t0
+        for r in range(nruns):
+            if seen[r] is None and st[r]["steady_step"] >= 0:
+                seen[r] = now
+        if all(s is not None for s in seen):
+            break
+    total = time.perf_counter() - t0
+    return [s["steady_step"] for s in st], seen, total, steps, [s["error_flags"] for s in st]
+
+
+def steady_bench(args) -> int:
+    """Wall time to the steady sheath (wall-potential detector) from cold
+    loads: all runs batched in one context, and the same runs one at a time
+    (a subset, the first --plain-runs)."""
+    import workloads
+    from paper_1511_08225_amd import autotune, slpic
+    cfgs = workloads.batched_sweep(nruns=args.runs, seed=1)
+    params = autotune.tune(cfgs, args.precision)
+    g = max(16, params["sort_every"])
+    block = g * max(1, 256 // g)
+    kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
+              chunk=params["chunk"], block=params["block"], graph_steps=g)
+    sim = slpic.Sim(cfgs, **kw)
+    b_steady, b_seen, b_total, b_steps, b_err = _to_steady(sim, len(cfgs), args.max_steps, block)
+    sim.close()
+    plain = []
+    for r in range(min(args.plain_runs, len(cfgs))):
+        one = slpic.Sim([dict(cfgs[r], run=0)], **kw)
+        s1, seen1, tot1, steps1, err1 = _to_steady(one, 1, args.max_steps, block)
+        one.close()
+        plain.append({"run": r, "steady_step": s1[0], "seconds": seen1[0] if seen1[0] is not None else tot1,
+                      "reached": seen1[0] is not None, "error_flags": err1[0]})
+    n_b = sum(1 for s in b_seen if s is not None)
+    plain_mean = sum(p["seconds"] for p in plain) / max(len(plain), 1)
+    print(json.dumps({
+        "metric": "time-to-steady-sheath, batched vs plain (cold start)", "unit": "s",
+        "runs": len(cfgs), "max_steps": args.max_steps, "block_steps": block, "tuned": params,
+        "batched": {"seconds_all": b_total, "steps": b_steps, "reached": n_b,
+                    "seconds_median_run": sorted(s for s in b_seen if s is not None)[n_b // 2] if n_b else None,
+                    "steady_steps": b_steady, "error_runs": [r for r, e in enumerate(b_err) if e]},
+        "plain": {"runs_measured": len(plain), "seconds_mean_per_run": plain_mean,
+                  "seconds_estimate_all": plain_mean * len(cfgs), "runs": plain},
+        "speedup_estimate": (plain_mean * len(cfgs)) / b_total if b_total > 0 else None,
+    }), flush=True)
+    return 0
+
+
 def run_timed(cfg, args, steps, warmup):
     import torch
     from paper_1511_08225_amd import slpic
@@ -153,6 +258,11 @@ def main() -> int:
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-variant", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="batched-sweep throughput (autotuned) and exit")
+    ap.add_argument("--runs", type=int, default=256, help="runs in the batched sweep")
+    ap.add_argument("--steady", action="store_true", help="time to the steady sheath, batched vs plain, and exit")
+    ap.add_argument("--plain-runs", type=int, default=16, help="runs timed one at a time in --steady")
+    ap.add_argument("--max-steps", type=int, default=16384, help="step cap in --steady")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the counter workload (copy calibration + direct-launch steps) and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -162,6 +272,10 @@ def main() -> int:
         return traffic_from(args.traffic_from[0], args.traffic_from[1], args.ppc, args.chunk)
     if args.traffic_probe:
         return traffic_probe(args)
+    if args.sweep:
+        return sweep_bench(args)
+    if args.steady:
+        return steady_bench(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2

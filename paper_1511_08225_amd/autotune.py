@@ -53,7 +53,8 @@ def _load_cache(path: str) -> dict:
 def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, warmup: int = 32) -> float:
     """Seconds per particle-step of the whole step (push, source, field,
     amortised sort) with these parameters, over `steps` graph-replayed steps
-    after `warmup` steps from the cold load."""
+    after `warmup` steps from the cold load; infinite if any run raised an
+    error flag (a sort period too long for its slot headroom overflows)."""
     se = params["sort_every"]
     g = max(16, se)
     steps = max(g, (steps // g) * g)
@@ -69,9 +70,10 @@ def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, 
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         pushes = sim.pushed_total() - p0
+        flagged = any(s["error_flags"] for s in sim.status())
     finally:
         sim.close()
-    return dt / max(pushes, 1)
+    return math.inf if flagged else dt / max(pushes, 1)
 
 
 def tune(configs: list[dict], precision: str = "f32", cache_path: str = CACHE_PATH, force: bool = False,

@@ -84,10 +84,13 @@ PRODUCTION_U_SWEEP = (2.0, 5.0, 10.0, math.inf)
 
 
 def batched_sweep(nruns: int = 256, seed: int = 1, ppc_range=(200, 1000), cells_range=(128, 2048),
-                  **kw) -> list[dict]:
+                  capacity_factor: float = 2.5, **kw) -> list[dict]:
     """Independent 1D sheaths: cells uniform in [128, 2048], ppc uniform in
     [200, 1000], Te/Ti log-uniform in [5, 100], ion mass in {4, 20, 40, 84}
-    amu, u uniform in [2, 10] v_ti; dx = 0.5 so L/lambda_D = cells/2."""
+    amu, u uniform in [2, 10] v_ti; dx = 0.5 so L/lambda_D = cells/2.  Slots
+    per species are 2.5x the load: small runs lose most of their ions within
+    a few hundred steps, and between two sorts the holes stay occupied while
+    the source appends."""
     rng = np.random.default_rng(seed)
     runs = []
     for r in range(nruns):
@@ -97,7 +100,7 @@ def batched_sweep(nruns: int = 256, seed: int = 1, ppc_range=(200, 1000), cells_
         amu = float(rng.choice([4.0, 20.0, 40.0, 84.0]))
         k = float(rng.uniform(2.0, 10.0))
         runs.append(sheath(nx=nx, ppc=ppc, u_over_vti=k, te_over_ti=te_ti, ion_amu=amu,
-                           seed=seed * 100003 + r, run=r, **kw))
+                           seed=seed * 100003 + r, run=r, capacity_factor=capacity_factor, **kw))
     return runs
 
 
