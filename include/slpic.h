@@ -227,6 +227,51 @@ void slpic_destroy(void* ctx);
 /* Static description of an SLPIC_* code. */
 const char* slpic_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network (not in the paper): 4 -> 256 -> 256 -> 256 -> 1280,
+ * ReLU after the hidden layers, mapping standardised sheath parameters to
+ * standardised steady profiles.  BF16 weights, biases, inputs and stored
+ * activations (round to nearest even from FP32), FP32 accumulation on the
+ * matrix cores.  Parameter vector, element offsets identical in the BF16
+ * and the FP32 copy: W1 [256][4], b1 [256], W2 [256][256], b2 [256],
+ * W3 [256][256], b3 [256], W4 [1280][256], b4 [1280].  The caller owns every
+ * buffer; batch must be a positive multiple of 16.  All calls are async on
+ * stream and return SLPIC_EINVAL on bad arguments.
+ * ------------------------------------------------------------------------ */
+#define SLPIC_MLP_IN 4
+#define SLPIC_MLP_HIDDEN 256
+#define SLPIC_MLP_OUT 1280
+#define SLPIC_MLP_PARAMS 461824
+
+/* Bytes of the activation buffer written by forward and read by backward
+ * (BF16 inputs and the three hidden activations), and of backward's
+ * scratch buffer (BF16 output and hidden gradients). */
+size_t slpic_mlp_act_bytes(int32_t batch);
+size_t slpic_mlp_work_bytes(int32_t batch);
+
+/* d_params_bf16 (uint16 BF16 bits) = BF16 rounding of d_params_fp32. */
+int slpic_mlp_to_bf16(const float* d_params_fp32, void* d_params_bf16, void* stream);
+
+/* d_y [batch][1280] (FP32) from d_x [batch][4] (FP32); d_act receives the
+ * activations backward needs. */
+int slpic_mlp_forward(const void* d_params_bf16, const float* d_x, float* d_y, int32_t batch, void* d_act,
+                      void* stream);
+
+/* d_grads [SLPIC_MLP_PARAMS] (FP32, overwritten) = gradient of
+ * sum(d_dy * y) for the batch whose activations forward left in d_act. */
+int slpic_mlp_backward(const void* d_params_bf16, const void* d_act, const float* d_dy, float* d_grads,
+                       int32_t batch, void* d_work, void* stream);
+
+/* Mean squared error over n values: d_dy = 2 (y - t) / n, and the loss
+ * sum (y - t)^2 / n added to *d_loss (one FP32, zeroed by the caller). */
+int slpic_mlp_mse(const float* d_y, const float* d_t, float* d_dy, int64_t n, float* d_loss, void* stream);
+
+/* One Adam step (step counts from 1) on the FP32 master parameters with
+ * moment buffers d_m, d_v (FP32, zero before step 1), refreshing the BF16
+ * copy. */
+int slpic_mlp_adam(float* d_params_fp32, void* d_params_bf16, float* d_m, float* d_v, const float* d_grads,
+                   float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,7 @@ UNITS = {
     "kernels_f64.hip": ["-ffp-contract=off"],
     "kernels_common.hip": ["-ffp-contract=off"],
     "api.cpp": ["-x", "hip"],
+    "mlp.hip": [],
 }
 
 

@@ -90,6 +90,14 @@ def lib():
             "slpic_step": (ctypes.c_int, [_P, i32, _P]),
             "slpic_moments": (ctypes.c_int, [_P, i32, _P, _P]),
             "slpic_moments_sample": (ctypes.c_int, [_P, i32, _P]),
+            "slpic_mlp_act_bytes": (ctypes.c_size_t, [i32]),
+            "slpic_mlp_work_bytes": (ctypes.c_size_t, [i32]),
+            "slpic_mlp_to_bf16": (ctypes.c_int, [_P, _P, _P]),
+            "slpic_mlp_forward": (ctypes.c_int, [_P, _P, _P, i32, _P, _P]),
+            "slpic_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, i32, _P, _P]),
+            "slpic_mlp_mse": (ctypes.c_int, [_P, _P, _P, i64, _P, _P]),
+            "slpic_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                                              ctypes.c_float, ctypes.c_float, i32, _P]),
             "slpic_moments_window": (ctypes.c_int, [_P, i32, _P, i32, _P]),
             "slpic_status_query": (ctypes.c_int, [_P, ctypes.POINTER(RunStatus), i32]),
             "slpic_export_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, _PI64]),
@@ -302,3 +310,73 @@ def fixed_point_round(xt: np.ndarray, fixed_bits: int) -> np.ndarray:
     scale = math.ldexp(1.0, fixed_bits)
     q = np.rint(xt * scale) / scale
     return np.where(xt < 0, -1.0, q)
+
+
+# ---------------------------------------------------------------- warm-start network
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 4, 256, 1280, 461824
+
+
+class Mlp:
+    """The warm-start network's buffers (torch tensors on the device) and
+    its library calls: forward, backward and Adam run in the HIP kernels."""
+
+    def __init__(self, params_fp32, batch: int, device="cuda"):
+        if batch <= 0 or batch % 16:
+            raise SlpicError("batch must be a positive multiple of 16")
+        self.device = torch.device(device)
+        self.batch = int(batch)
+        self.p32 = torch.as_tensor(params_fp32, dtype=torch.float32).to(self.device).contiguous()
+        if self.p32.numel() != MLP_PARAMS:
+            raise SlpicError("parameter vector has the wrong length")
+        self.pbf16 = torch.empty(MLP_PARAMS, dtype=torch.int16, device=self.device)
+        self.m = torch.zeros_like(self.p32)
+        self.v = torch.zeros_like(self.p32)
+        self.grads = torch.zeros_like(self.p32)
+        L = lib()
+        self.act = torch.empty(L.slpic_mlp_act_bytes(self.batch), dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(L.slpic_mlp_work_bytes(self.batch), dtype=torch.uint8, device=self.device)
+        self.y = torch.empty((self.batch, MLP_OUT), dtype=torch.float32, device=self.device)
+        self.step = 0
+        _check(L.slpic_mlp_to_bf16(_P(self.p32.data_ptr()), _P(self.pbf16.data_ptr()), self._stream()),
+               "slpic_mlp_to_bf16")
+
+    def _stream(self):
+        return _P(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, x) -> torch.Tensor:
+        """y [batch][1280] from x [batch][4] (FP32, standardised)."""
+        x = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
+        if tuple(x.shape) != (self.batch, MLP_IN):
+            raise SlpicError("x must be [batch][4]")
+        self._x = x
+        _check(lib().slpic_mlp_forward(_P(self.pbf16.data_ptr()), _P(x.data_ptr()), _P(self.y.data_ptr()),
+                                       self.batch, _P(self.act.data_ptr()), self._stream()), "slpic_mlp_forward")
+        return self.y
+
+    def backward(self, dy) -> torch.Tensor:
+        """FP32 gradient of sum(dy * y) for the last forward batch."""
+        dy = torch.as_tensor(dy, dtype=torch.float32).to(self.device).contiguous()
+        _check(lib().slpic_mlp_backward(_P(self.pbf16.data_ptr()), _P(self.act.data_ptr()), _P(dy.data_ptr()),
+                                        _P(self.grads.data_ptr()), self.batch, _P(self.work.data_ptr()),
+                                        self._stream()), "slpic_mlp_backward")
+        return self.grads
+
+    def mse_backward(self, target) -> float:
+        """Loss of the last forward batch against target (MSE), and the
+        backward pass of its gradient; returns the loss (synchronises)."""
+        t = torch.as_tensor(target, dtype=torch.float32).to(self.device).contiguous()
+        if not hasattr(self, "_dy"):
+            self._dy = torch.empty_like(self.y)
+            self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self._loss.zero_()
+        _check(lib().slpic_mlp_mse(_P(self.y.data_ptr()), _P(t.data_ptr()), _P(self._dy.data_ptr()), self.y.numel(),
+                                   _P(self._loss.data_ptr()), self._stream()), "slpic_mlp_mse")
+        self.backward(self._dy)
+        return float(self._loss.item())
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        _check(lib().slpic_mlp_adam(_P(self.p32.data_ptr()), _P(self.pbf16.data_ptr()), _P(self.m.data_ptr()),
+                                    _P(self.v.data_ptr()), _P(self.grads.data_ptr()), float(lr), float(beta1),
+                                    float(beta2), float(eps), self.step, self._stream()), "slpic_mlp_adam")
+
