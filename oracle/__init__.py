@@ -113,6 +113,10 @@ def lib():
             "orc_set_counters": (None, [_VP, _I64, _D]),
             "orc_get_grid": (None, [_VP, _PD, _PD, _PD, _PD]),
             "orc_get_steady": (None, [_VP, ctypes.POINTER(_Steady)]),
+            "orc_load_warm": (ctypes.c_int, [_VP, _PD]),
+            "orc_warm_cell_count": (_I64, [ctypes.POINTER(_Config), ctypes.c_int, _PD, ctypes.c_int32, _D, _PD]),
+            "orc_warm_particle": (None, [ctypes.POINTER(_Config), ctypes.c_int, ctypes.c_uint32, ctypes.c_int32, _D,
+                                         _PD]),
             "orc_steady_init": (None, [ctypes.POINTER(_Steady), ctypes.c_int32, _D]),
             "orc_steady_feed": (None, [ctypes.POINTER(_Steady), _D, _I64]),
         }
@@ -170,6 +174,22 @@ def steady_detect(series, window: int, tol: float) -> dict:
     for k, v in enumerate(series):
         lib().orc_steady_feed(ctypes.byref(d), float(v), k + 1)
     return d.as_dict()
+
+
+def warm_cell_count(cfg: dict, s: int, profile, c: int, w: float):
+    """(g-particle count, drift V) of cell c, species s, of a warm load."""
+    prof = np.ascontiguousarray(np.asarray(profile, dtype=np.float64).reshape(5, 256))
+    V = ctypes.c_double(0.0)
+    c_ = make_config(cfg)
+    n = lib().orc_warm_cell_count(ctypes.byref(c_), int(s), _dp(prof), int(c), float(w), ctypes.byref(V))
+    return int(n), V.value
+
+
+def warm_particle(cfg: dict, s: int, i: int, c: int, V: float):
+    out = (ctypes.c_double * 4)()
+    c_ = make_config(cfg)
+    lib().orc_warm_particle(ctypes.byref(c_), int(s), int(i) & 0xffffffff, int(c), float(V), out)
+    return list(out)
 
 
 # ---------------------------------------------------------------- primitives
@@ -249,13 +269,18 @@ def poisson1d(nx: int, dx: float, Q: np.ndarray):
 class Run:
     """One 1D3V SLPIC run on the CPU (FP64)."""
 
-    def __init__(self, cfg: dict, load: bool = True):
+    def __init__(self, cfg: dict, load: bool = True, warm=None):
+        """warm: optional (5, 256) profiles (phi, n_e, n_i, Gamma_e, Gamma_i on
+        x/L = k/255) for a warm load instead of the cold one."""
         self.cfg = dict(cfg)
         self._c = make_config(cfg)
         self._h = lib().orc_create(ctypes.byref(self._c))
         self.nx = self._c.nx
         self.nspecies = self._c.nspecies
-        if load:
+        if warm is not None:
+            prof = np.ascontiguousarray(np.asarray(warm, dtype=np.float64).reshape(5, 256))
+            lib().orc_load_warm(self._h, _dp(prof))
+        elif load:
             lib().orc_load(self._h)
 
     def __del__(self):

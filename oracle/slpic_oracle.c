@@ -632,6 +632,132 @@ void orc_load(orc_run* r) {
     orc_refresh_fields(r);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Warm load from predicted steady profiles (a reading; the paper loads     */
+/* cold).  profile: 5 x 256 values on x/L = k/255: phi, n_e, n_i, Gamma_e,    */
+/* Gamma_i (physical).  In cell c (centre x/L = (c + 1/2)/nx), species s:    */
+/* n and Gamma by linear interpolation (n clamped at 0), drift              */
+/* V = Gamma/n clamped to |V| <= 4 vt, f = n Maxwellian(V e_x, vt) and       */
+/* g = f/beta (Eq. 5): the cell holds E = n dx Z / w g-particles, Z = <1/beta> */
+/* over the drifting Maxwellian, w the run's constant weight; the count is   */
+/* floor(E) + [U < frac(E)].  Positions uniform in the cell; velocities from */
+/* f/beta by rejection from the drifting Maxwellian against                  */
+/* M = 1/beta(|V| + 8 vt) (a proposal beyond 8 vt is accepted).  Particles   */
+/* are stored cell by cell.                                                  */
+/* ------------------------------------------------------------------------ */
+static double inv_beta(int kind, double u, double s) {
+    if (isinf(u)) return 1.0;
+    if (kind == ORC_BETA_SMOOTH) return sqrt(1.0 + (s / u) * (s / u));
+    return s <= u ? 1.0 : s / u;
+}
+
+/* Density of |v| for v = V e_x + vt z (z standard normal in 3D):
+ * p(s) = s/(vt sqrt(2 pi)) exp(-(s - V)^2 / (2 vt^2)) (1 - exp(-2 s V / vt^2)) / V,
+ * whose V -> 0 limit is the Maxwell speed density. */
+static double drift_speed_density(double s, double V, double vt) {
+    double a = s / (vt * sqrt(TWO_PI)) * exp(-(s - V) * (s - V) / (2.0 * vt * vt));
+    double q = 2.0 * s * V / (vt * vt);
+    double f = q > 1e-300 ? -expm1(-q) / V : 2.0 * s / (vt * vt);
+    return a * f;
+}
+
+/* Z = <1/beta> over the drifting Maxwellian: composite Simpson, 4096 panels,
+ * on [lo, hi] with hi = |V| + 12 vt (beyond: < 1e-30 of the mass); for the
+ * step form the integrand is 1 below u, so Z = 1 + int_u^hi (s/u - 1) p. */
+static double warm_Z(int kind, double u, double V, double vt) {
+    if (isinf(u)) return 1.0;
+    V = fabs(V);
+    double hi = V + 12.0 * vt;
+    int n = 4096;
+    double lo = 0.0;
+    if (kind == ORC_BETA_STEP) {
+        if (u >= hi) return 1.0;
+        lo = u;
+    }
+    double h = (hi - lo) / n, acc = 0.0;
+    for (int k = 0; k <= n; ++k) {
+        double s = lo + h * k;
+        double g = (kind == ORC_BETA_STEP) ? (s / u - 1.0) : sqrt(1.0 + (s / u) * (s / u));
+        double w = (k == 0 || k == n) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+        acc += w * g * drift_speed_density(s, V, vt);
+    }
+    acc *= h / 3.0;
+    return kind == ORC_BETA_STEP ? 1.0 + acc : acc;
+}
+
+static double interp_profile(const double* p, double xi) {
+    double t = xi * 255.0;
+    int k = (int)floor(t);
+    if (k < 0) k = 0;
+    if (k > 254) k = 254;
+    double f = t - (double)k;
+    return p[k] * (1.0 - f) + p[k + 1] * f;
+}
+
+int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile, int32_t c, double w,
+                            double* V_out) {
+    double vt = species_vt(cfg, s);
+    double xi = ((double)c + 0.5) / (double)cfg->nx;
+    const double* pn = profile + 256 * (s == 0 ? 1 : 2);
+    const double* pg = profile + 256 * (s == 0 ? 3 : 4);
+    double n = interp_profile(pn, xi);
+    if (!(n > 0.0)) n = 0.0;
+    double G = interp_profile(pg, xi);
+    double V = n > 0.0 ? G / n : 0.0;
+    if (V > 4.0 * vt) V = 4.0 * vt;
+    if (V < -4.0 * vt) V = -4.0 * vt;
+    if (V_out) *V_out = V;
+    double E = n * cfg->dx * warm_Z(cfg->beta_kind, cfg->u, V, vt) / w;
+    double fl = floor(E);
+    orc_stream st;
+    stream_init(&st, cfg, (uint32_t)c, 0u, ORC_PURPOSE_WARM_COUNT, s);
+    return (int64_t)fl + (stream_next(&st) < E - fl ? 1 : 0);
+}
+
+void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double out[4]) {
+    orc_stream st;
+    stream_init(&st, cfg, i, 0u, ORC_PURPOSE_WARM, s);
+    double vt = species_vt(cfg, s);
+    double u = cfg->u;
+    out[0] = (double)c + stream_next(&st);
+    if (out[0] >= (double)(c + 1)) out[0] = nextafter((double)(c + 1), 0.0);
+    double M = inv_beta(cfg->beta_kind, u, fabs(V) + 8.0 * vt);
+    double v[3] = {V, 0.0, 0.0};
+    for (int attempt = 0; attempt < 100000; ++attempt) {
+        double z[3];
+        stream_normal3(&st, z);
+        v[0] = V + vt * z[0];
+        v[1] = vt * z[1];
+        v[2] = vt * z[2];
+        double sp = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        double w = inv_beta(cfg->beta_kind, u, sp);
+        if (w >= M || stream_next(&st) * M < w) break;
+    }
+    out[1] = v[0]; out[2] = v[1]; out[3] = v[2];
+}
+
+int orc_load_warm(orc_run* r, const double* profile) {
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        int64_t i = 0;
+        for (int32_t c = 0; c < r->cfg.nx; ++c) {
+            double V;
+            int64_t cnt = orc_warm_cell_count(&r->cfg, s, profile, c, r->w[s], &V);
+            ensure_capacity(r, s, i + cnt);
+            for (int64_t k = 0; k < cnt; ++k, ++i) {
+                double p[4];
+                orc_warm_particle(&r->cfg, s, (uint32_t)i, c, V, p);
+                r->x[s][i] = p[0]; r->vx[s][i] = p[1]; r->vy[s][i] = p[2]; r->vz[s][i] = p[3];
+            }
+        }
+        r->n[s] = i;
+    }
+    r->step = 0;
+    r->acc_e = 0.0;
+    if (r->cfg.sort_every > 0) orc_sort(r, NULL, NULL);
+    orc_refresh_fields(r);
+    return 0;
+}
+
 static void inject(orc_run* r, int s, int64_t count) {
     ensure_capacity(r, s, r->n[s] + count);
     for (int64_t k = 0; k < count; ++k) {

@@ -30,7 +30,7 @@ extern "C" {
 
 enum { ORC_BETA_STEP = 0, ORC_BETA_SMOOTH = 1 };
 enum { ORC_KICK_EXACT = 0, ORC_KICK_MMP = 1 };
-enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2 };
+enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2, ORC_PURPOSE_WARM_COUNT = 3, ORC_PURPOSE_WARM = 4 };
 
 typedef struct {
     double charge, mass, temperature;
@@ -106,6 +106,13 @@ void orc_destroy(orc_run* r);
 void orc_load(orc_run* r);
 void orc_refresh_fields(orc_run* r);
 void orc_step(orc_run* r, int32_t nsteps);
+/* Warm load (replaces the particles, resets the counters, sorts if sorting
+ * is on and refreshes the fields): profile = 5 x 256 doubles on x/L = k/255,
+ * phi, n_e, n_i, Gamma_e, Gamma_i. */
+int orc_load_warm(orc_run* r, const double* profile);
+int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile, int32_t c, double w,
+                            double* V_out);
+void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double out[4]);
 void orc_sort(orc_run* r, int32_t* perm0, int32_t* perm1);
 void orc_keys(const orc_run* r, int32_t s, int32_t* keys);
 void orc_moments(const orc_run* r, double* out);

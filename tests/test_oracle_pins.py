@@ -589,3 +589,75 @@ def test_steady_detector_matches_run_history():
     assert got["steady_step"] == d["steady_step"]
     assert got["windows"] == d["windows"] == 200 // (cfg["nx"] // 4)
     assert got["window_mean"] == d["window_mean"]
+
+
+# ---------------------------------------------------------------- warm load
+def _uniform_profile(n=1.0, gamma=0.0):
+    p = np.zeros((5, 256))
+    p[1] = p[2] = n
+    p[3] = p[4] = gamma
+    return p
+
+
+def test_warm_load_uniform_profile_reproduces_cold_counts():
+    """A uniform, drift-free profile at n0 = 1: every cell holds ppc
+    g-particles, as the cold load does on average (the warm Z by quadrature
+    equals the closed-form Z of the weight)."""
+    for kind in ("step", "smooth"):
+        cfg = workloads.sheath(nx=16, ppc=50, u_over_vti=3.0, dt=5.0, beta_kind=kind)
+        w = oracle.Run(cfg, load=False).weights()
+        for s in range(2):
+            for c in (0, 7, 15):
+                cnt, V = oracle.warm_cell_count(cfg, s, _uniform_profile(), c, w[s])
+                assert cnt == 50 and V == 0.0, (kind, s, c, cnt)
+
+
+def test_warm_Z_with_drift_against_cylindrical_quadrature():
+    """<1/beta> over a drifting Maxwellian, integrated in cylindrical
+    velocity coordinates (SciPy), fixes the expected cell count
+    E = n dx Z / w that the loader's count is the floor or ceiling of."""
+    cfg = workloads.sheath(nx=16, ppc=40, u_over_vti=3.0, dt=5.0)
+    run = oracle.Run(cfg, load=False)
+    w = run.weights()
+    vt = math.sqrt(cfg["species"][1]["temperature"] / cfg["species"][1]["mass"])
+    u = cfg["u"]
+    for V_over_vt in (0.0, 0.7, 2.5):
+        V = V_over_vt * vt
+        prof = _uniform_profile(n=0.8, gamma=0.8 * V)
+        inv_beta = lambda sp: 1.0 if sp <= u else sp / u
+        dens = lambda r, a: (math.exp(-(a - V) ** 2 / (2 * vt * vt)) / (vt * math.sqrt(2 * math.pi))
+                             * r / (vt * vt) * math.exp(-r * r / (2 * vt * vt)))
+        Z, _ = integrate.dblquad(lambda r, a: inv_beta(math.hypot(a, r)) * dens(r, a),
+                                 V - 12 * vt, V + 12 * vt, 0.0, 12 * vt, epsabs=1e-12, epsrel=1e-11)
+        E = 0.8 * cfg["dx"] * Z / w[1]
+        cnt, Vo = oracle.warm_cell_count(cfg, 1, prof, 5, w[1])
+        assert Vo == pytest.approx(V, rel=1e-12, abs=1e-300)
+        assert cnt in (math.floor(E), math.floor(E) + 1), (V_over_vt, cnt, E)
+
+
+def test_warm_load_reproduces_profile_moments():
+    """The physical moments of a warm-loaded state (f = beta g, Eq. 5) match
+    the profile it was drawn from: density and flux within statistics."""
+    cfg = workloads.sheath(nx=32, ppc=2000, u_over_vti=3.0, dt=5.0, sort_every=1)
+    xi = np.arange(256) / 255.0
+    vte = 1.0
+    vti = math.sqrt(cfg["species"][1]["temperature"] / cfg["species"][1]["mass"])
+    prof = np.zeros((5, 256))
+    prof[1] = 1.0 + 0.5 * np.cos(math.pi * xi)     # n_e
+    prof[2] = prof[1]                              # n_i
+    prof[3] = prof[1] * 0.3 * vte * xi             # Gamma_e: drift 0.3 v_te at the wall
+    prof[4] = prof[2] * 1.5 * vti * xi             # Gamma_i: drift 1.5 v_ti at the wall
+    run = oracle.Run(cfg, warm=prof)
+    M = run.moments()
+    nodes = np.arange(cfg["nx"] + 1) / cfg["nx"]
+    inner = slice(2, cfg["nx"] - 1)                # end nodes see half a cell
+    for s, (nrow, grow) in enumerate(((1, 3), (4, 6))):
+        n_want = np.interp(nodes, xi, prof[1 + s])
+        g_want = np.interp(nodes, xi, prof[3 + s])
+        n_got, g_got = M[nrow], M[grow - 1]
+        rel = np.abs(n_got[inner] - n_want[inner]) / n_want[inner]
+        assert rel.mean() < 0.02 and rel.max() < 0.08, (s, rel.mean(), rel.max())
+        # the flux estimate is noisy per node (each g-particle carries at most
+        # w u of it): compare its average over the inner nodes
+        avg_got, avg_want = g_got[inner].mean(), g_want[inner].mean()
+        assert avg_got == pytest.approx(avg_want, rel=0.08), (s, avg_got, avg_want)
