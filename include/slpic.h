@@ -91,6 +91,13 @@ typedef struct {
     double steady_tol;     /* steady when the last three window means of Phi_w  */
                            /* lie within steady_tol * |their mean| of it;       */
                            /* 0 = default 0.02                                  */
+    const double* warm_profile; /* NULL: cold load.  Else a host array of 5 x 256 */
+                           /* doubles on x/L = k/255 (k = 0..255): phi, n_e,    */
+                           /* n_i, Gamma_e, Gamma_i (physical), read by          */
+                           /* slpic_workspace_bytes and slpic_init only: each    */
+                           /* cell is loaded from the Maxwellian drifting at     */
+                           /* V = Gamma/n (|V| <= 4 vt) with n dx <1/beta>/w     */
+                           /* g-particles sampled as f/beta (Eq. 5)             */
 } slpic_run_config;
 
 typedef struct {
@@ -126,7 +133,8 @@ typedef struct {
  * given tuning (NULL = defaults).  Returns 0 on an invalid configuration. */
 size_t slpic_workspace_bytes(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* tuning);
 
-/* Create a context over the caller's workspace and load every run cold:
+/* Create a context over the caller's workspace and load every run cold
+ * (or warm, from its warm_profile):
  * g0 = f0/beta (Eq. 5) sampled with Philox4x32-10 from each run's seed,
  * weight dx Z/ppc with Z = <1/beta> over the Maxwellian; then (if sort_every
  * > 0) the first cell sort, the beta-weighted deposit of rho^0 (Eq. A2c) and

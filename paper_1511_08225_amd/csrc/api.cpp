@@ -13,6 +13,7 @@
 
 #include "slpic.h"
 #include "launch.h"
+#include "slpic_device.h"
 #include "slpic_internal.h"
 
 using namespace slpic;
@@ -30,6 +31,98 @@ void step_mixture(double ut, double& Ps, double& Pf) {
     double e = std::exp(-0.5 * ut * ut);
     Ps = std::erf(ut / std::sqrt(2.0)) - c * ut * e;
     Pf = c * (ut * ut + 2.0) * e / ut;
+}
+
+// ---------------------------------------------------------------------------
+// Warm load planning.  For cell c of species s: n and Gamma linearly
+// interpolated from the 256-point profiles (x/L = k/255) at the cell centre,
+// n clamped at 0, drift V = Gamma/n clamped to |V| <= 4 vt; the expected
+// g-particle count is E = n dx Z / w with Z = <1/beta> over the Maxwellian
+// drifting at V (f = beta g, Eq. 5), rounded up with probability frac(E)
+// by the cell's Philox uniform.
+// ---------------------------------------------------------------------------
+struct GaussLegendre {
+    static constexpr int n = 64;
+    double x[n], w[n];  // on [-1, 1]
+    GaussLegendre() {
+        for (int i = 0; i < n; ++i) {
+            double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1.0, p1 = z;  // Legendre recurrence to P_n and its derivative
+                for (int k = 2; k <= n; ++k) {
+                    double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = pk;
+                }
+                dp = n * (z * p1 - p0) / (z * z - 1.0);
+                const double dz = p1 / dp;
+                z -= dz;
+                if (std::fabs(dz) < 1e-16) break;
+            }
+            x[i] = z;
+            w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+};
+
+// Density of |v| for v = V e_x + vt z, z standard normal in 3D (V -> 0: Maxwell).
+static double drift_speed_pdf(double sp, double V, double vt) {
+    const double g = sp / (vt * std::sqrt(2.0 * M_PI)) * std::exp(-(sp - V) * (sp - V) / (2.0 * vt * vt));
+    const double q = 2.0 * sp * V / (vt * vt);
+    return g * (q > 1e-300 ? -std::expm1(-q) / V : 2.0 * sp / (vt * vt));
+}
+
+// <1/beta> over the Maxwellian drifting at V: 64-point Gauss-Legendre in the
+// speed on [lo, |V| + 12 vt] (lo = u for Eq. 11b, whose integrand is 1 below u).
+static double drift_mean_inv_beta(int kind, double u, double V, double vt) {
+    static const GaussLegendre gl;
+    if (std::isinf(u)) return 1.0;
+    V = std::fabs(V);
+    const double hi = V + 12.0 * vt;
+    const double lo = kind == SLPIC_BETA_STEP ? u : 0.0;
+    if (lo >= hi) return 1.0;
+    const double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+    double acc = 0.0;
+    for (int i = 0; i < gl.n; ++i) {
+        const double sp = mid + half * gl.x[i];
+        const double f = kind == SLPIC_BETA_STEP ? sp / u - 1.0 : std::sqrt(1.0 + (sp / u) * (sp / u));
+        acc += gl.w[i] * f * drift_speed_pdf(sp, V, vt);
+    }
+    acc *= half;
+    return kind == SLPIC_BETA_STEP ? 1.0 + acc : acc;
+}
+
+static double profile_at(const double* p, double xi) {
+    const double t = xi * 255.0;
+    int k = (int)std::floor(t);
+    k = std::max(0, std::min(254, k));
+    const double f = t - (double)k;
+    return p[k] * (1.0 - f) + p[k + 1] * f;
+}
+
+// Cells of one (run, species), appended to out; returns the particle count.
+static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, int run, int s,
+                                 std::vector<WarmCell>& out) {
+    const double* pn = c.warm_profile + 256 * (s == 0 ? 1 : 2);
+    const double* pg = c.warm_profile + 256 * (s == 0 ? 3 : 4);
+    const double vt = R.vt[s];
+    int64_t start = 0;
+    for (int cell = 0; cell < c.nx; ++cell) {
+        const double xi = ((double)cell + 0.5) / (double)c.nx;
+        double n = profile_at(pn, xi);
+        if (!(n > 0.0)) n = 0.0;
+        const double G = profile_at(pg, xi);
+        double V = n > 0.0 ? G / n : 0.0;
+        V = std::max(-4.0 * vt, std::min(4.0 * vt, V));
+        const double E = n * c.dx * drift_mean_inv_beta(c.beta_kind, c.u, V, vt) / R.w[s];
+        const double fl = std::floor(E);
+        const U4 r = philox10((uint32_t)cell, 0u, R.run_id, ((uint32_t)kPurposeWarmCount << 24) | ((uint32_t)s << 20),
+                              R.seed_lo, R.seed_hi);
+        const int64_t cnt = (int64_t)fl + (u53(r.v[0], r.v[1]) < E - fl ? 1 : 0);
+        if (cnt > 0) out.push_back(WarmCell{run, s, cell, (int32_t)cnt, start, V});
+        start += cnt;
+    }
+    return start;
 }
 
 double mean_inv_beta(int kind, double ut) {
@@ -75,6 +168,7 @@ struct Plan {
     std::vector<Chunk> chunks;
     std::vector<int> run_chunk0, run_nchunks;
     std::vector<Tile> tiles;
+    std::vector<WarmCell> warm_cells;
     int64_t total_slots = 0, total_nodes = 0, hist_entries = 0;
     int max_nodes = 0, max_src = 0, max_nkeys = 0;
     Layout L{};
@@ -124,6 +218,9 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         R.dtdx = c.dt / c.dx;
         R.fscale = std::ldexp(1.0, R.fb);
         R.inv_fscale = std::ldexp(1.0, -R.fb);
+        R.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
+        R.seed_hi = (uint32_t)(c.seed >> 32);
+        R.run_id = (uint32_t)c.run_id;
         double cf = c.capacity_factor > 1.0 ? c.capacity_factor : 1.0;
         for (int s = 0; s < 2; ++s) {
             const slpic_species& sp = c.species[s];
@@ -142,7 +239,15 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
                 step_mixture(R.ut[s], R.Ps[s], R.Pf[s]);
             }
             R.nload[s] = (int64_t)c.nx * sp.ppc;
-            R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), R.nload[s] + 64);
+            if (c.warm_profile) {
+                R.warm = 1;
+                const int64_t nw = plan_warm_species(R, c, r, s, P.warm_cells);
+                if (nw > ((int64_t)1 << 31) - 65) return SLPIC_ECAPACITY;
+                R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), nw + 64);
+                R.nload[s] = nw;
+            } else {
+                R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), R.nload[s] + 64);
+            }
             if (R.cap[s] > (int64_t(1) << 31) - 1) return SLPIC_EINVAL;
             R.poff[s] = poff;
             poff += R.cap[s];
@@ -154,9 +259,6 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         if (c.steady_window < 0 || !(c.steady_tol >= 0.0)) return SLPIC_EINVAL;
         R.steady_window = c.steady_window > 0 ? c.steady_window : std::max(1, c.nx / 4);
         R.steady_tol = c.steady_tol > 0.0 ? c.steady_tol : 0.02;
-        R.seed_lo = (uint32_t)(c.seed & 0xffffffffu);
-        R.seed_hi = (uint32_t)(c.seed >> 32);
-        R.run_id = (uint32_t)c.run_id;
         R.goff = goff;
         goff += R.nodes;
         P.max_nodes = std::max(P.max_nodes, R.nodes);
@@ -500,6 +602,20 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     launch_zero(a.phi, c->P.total_nodes, s);
     launch_zero(a.history, (int64_t)kHistoryLen * nruns, s);
     l_load(c, s);
+    if (!c->P.warm_cells.empty()) {
+        // the table goes to the second particle buffer, unused until the first sort
+        const size_t tb = sizeof(WarmCell) * c->P.warm_cells.size();
+        const size_t room = (size_t)c->P.total_slots * (c->P.tun.precision == SLPIC_F32 ? 4 : 8);
+        if (tb > room) {
+            delete c;
+            return SLPIC_ENOMEM;
+        }
+        void* d_cells = w + L.x[1];
+        INIT_TRY(hipMemcpyAsync(d_cells, c->P.warm_cells.data(), tb, hipMemcpyHostToDevice, s) ? SLPIC_EHIP
+                                                                                               : SLPIC_OK);
+        if (prec(c) == SLPIC_F32) launch_load_warm_f32(a, d_cells, (int)c->P.warm_cells.size(), s);
+        else launch_load_warm_f64(a, d_cells, (int)c->P.warm_cells.size(), s);
+    }
     if (c->P.tun.sort_every > 0) INIT_TRY(do_sort(c, s));
     l_push(c, false, s);
     launch_field(a, nruns, 0, c->field_lds, s);

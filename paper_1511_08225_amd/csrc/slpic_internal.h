@@ -10,6 +10,8 @@ namespace slpic {
 constexpr int kMaxSpecies = 2;
 constexpr int kPurposeLoad = 1;
 constexpr int kPurposeInject = 2;
+constexpr int kPurposeWarmCount = 3;  // warm load: rounding of a cell's count
+constexpr int kPurposeWarm = 4;       // warm load: one particle
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
 constexpr int kCountSlots = 64;    // spread slots of the per-step particle counters
 
@@ -36,7 +38,7 @@ struct RunInfo {
     int32_t chunk0[kMaxSpecies]; // first push chunk of (run, species)
     int32_t nchunk[kMaxSpecies]; // push chunks of (run, species)
     int32_t steady_window;       // steps per wall-potential window
-    int32_t pad1;
+    int32_t warm;                // 1: loaded from predicted profiles (k_load_warm), not cold
     double steady_tol;           // relative spread of three window means that counts as steady
 };
 
@@ -69,6 +71,14 @@ struct InjectPlan {
     double acc_e;                   // carried fraction after this step
     int32_t overflow;               // capacity hit
     int32_t pad;
+};
+
+// One cell of a warm load: `count` particles of (run, species) at slots
+// start.., drawn from a Maxwellian drifting at V along x, as f/beta.
+struct WarmCell {
+    int32_t run, species, cell, count;
+    int64_t start;
+    double V;
 };
 
 // A contiguous slot range of one (run, species): one push / load / moments

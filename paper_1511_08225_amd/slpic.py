@@ -39,7 +39,7 @@ class RunConfig(ctypes.Structure):
                 ("nspecies", ctypes.c_int32), ("source_cells", ctypes.c_int32),
                 ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run_id", ctypes.c_int32),
                 ("steady_window", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
-                ("steady_tol", ctypes.c_double)]
+                ("steady_tol", ctypes.c_double), ("warm_profile", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -172,13 +172,26 @@ class Sim:
     """One or more independent 1D3V sheaths advanced together on one GPU."""
 
     def __init__(self, configs, precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0,
-                 graph_steps=0, sort_tile=0, device="cuda"):
+                 graph_steps=0, sort_tile=0, device="cuda", warm=None):
+        """warm: optional list (one entry per run) of None or a (5, 256)
+        array of predicted profiles (phi, n_e, n_i, Gamma_e, Gamma_i on
+        x/L = k/255) for a warm load instead of the cold one."""
         if isinstance(configs, dict):
             configs = [configs]
         self.configs = [dict(c) for c in configs]
         self.nruns = len(self.configs)
         self.precision = precision
         self._cfg = (RunConfig * self.nruns)(*[run_config(c) for c in self.configs])
+        self._warm = []  # host profiles, alive while the library reads them
+        if warm is not None:
+            if len(warm) != self.nruns:
+                raise SlpicError("warm needs one entry per run")
+            for r, prof in enumerate(warm):
+                if prof is None:
+                    continue
+                a = np.ascontiguousarray(np.asarray(prof, dtype=np.float64).reshape(5, 256))
+                self._warm.append(a)
+                self._cfg[r].warm_profile = a.ctypes.data
         self._tun = tuning(precision, sort_every, sort_bucket, chunk, block, graph_steps, sort_tile)
         L = lib()
         nbytes = L.slpic_workspace_bytes(self._cfg, self.nruns, ctypes.byref(self._tun))

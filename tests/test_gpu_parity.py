@@ -73,6 +73,50 @@ def test_cold_load_matches_oracle(gpu_lib):
             sim.close()
 
 
+def _warm_profile(nx_phys_scale=1.0):
+    xi = np.arange(256) / 255.0
+    p = np.zeros((5, 256))
+    p[0] = 5.0 * (1 - xi ** 2)
+    p[1] = 1.0 + 0.5 * np.cos(math.pi * xi)
+    p[2] = p[1] * (1.0 + 0.05 * xi)
+    p[3] = p[1] * 0.2 * xi
+    p[4] = p[2] * 0.004 * xi * nx_phys_scale
+    return p
+
+
+def test_warm_load_matches_oracle(gpu_lib):
+    """Warm load from a smooth profile (density, drifts): per-cell counts and
+    positions as in the oracle, velocities to 1e-12 but for a few rejection
+    flips from last-bit libm differences; a cold run beside it in the same
+    context is unaffected."""
+    prof = _warm_profile()
+    for prec in ("f64", "f32"):
+        for kind, k in (("step", 3.0), ("smooth", 3.0), ("step", math.inf)):
+            cfg = workloads.sheath(nx=64, ppc=100, u_over_vti=k, dt=5.0 if k < 1e9 else 0.1,
+                                   beta_kind=kind, sort_every=0, seed=12)
+            cold = dict(cfg, run=1, seed=13)
+            print_case(f"warm load {prec} {kind} u/vti={k}")
+            sim = gpu_lib.Sim([cfg, cold], precision=prec, sort_every=0, warm=[prof, None])
+            run = oracle.Run(cfg, warm=prof)
+            run_cold = oracle.Run(cold)
+            st = sim.status()
+            for r, orun in ((0, run), (1, run_cold)):
+                for s in range(2):
+                    xg, vxg, vpg = sim.export_particles(r, s)
+                    xo, vxo, vpo = oracle_state(orun, s)
+                    if prec == "f32":
+                        xo, vxo, vpo = quantize_for_f32(xo, vxo, vpo, st[r]["fixed_bits"])
+                    assert len(xg) == len(xo), (r, s, len(xg), len(xo))
+                    assert np.array_equal(xg, xo)
+                    bad = ~(np.isclose(vxg, vxo, rtol=1e-12, atol=0) & np.isclose(vpg, vpo, rtol=1e-12, atol=0))
+                    assert bad.sum() <= 3, (r, s, bad.sum())
+            if prec == "f64":
+                g, o = sim.grid(0), run.grid()
+                for s in range(2):
+                    assert rel_inf(g["Q"][s], o["Q"][s]) <= 1e-9
+            sim.close()
+
+
 def test_deposit_and_field_match_oracle_f64(gpu_lib):
     cfg = workloads.small_sheath(sort_every=0)
     run = oracle.Run(cfg)
