@@ -169,6 +169,12 @@ int slpic_moments_window(void* ctx, int32_t run, double* d_out, int32_t reset, v
 /* Sync.  Copies the status of runs [0, nruns) to h_out. */
 int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns);
 
+/* Sync.  The wall potential Phi_w after each of the last min(step, 4096)
+ * steps of one run, oldest first, to h_out (at least 4096 doubles); *n
+ * receives the count.  Step k (1-based) of the run is entry n - (step - k) - 1. */
+#define SLPIC_HISTORY_LEN 4096
+int slpic_wall_history(void* ctx, int32_t run, double* h_out, int64_t* n);
+
 /* Sync.  Copies the nslots occupied slots of (run, species) to host arrays
  * of at least *n doubles: xt = x/dx (dead slots < 0), v_x and v_perp^2 =
  * v_y^2 + v_z^2.  On entry *n is the host capacity; on return the count.

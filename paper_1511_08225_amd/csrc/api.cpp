@@ -728,6 +728,22 @@ int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns) {
     return SLPIC_OK;
 }
 
+int slpic_wall_history(void* ctx, int32_t run, double* h_out, int64_t* n) {
+    Context* c = ctx_of(ctx);
+    if (!c || !h_out || !n || run < 0 || run >= c->P.nruns) return SLPIC_EINVAL;
+    static_assert(kHistoryLen == SLPIC_HISTORY_LEN, "history length");
+    HIP_TRY(hipDeviceSynchronize());
+    int64_t step = 0;
+    if (int rc = copy_d2h(&step, &c->a.state[run].step, sizeof step)) return rc;
+    std::vector<double> ring(kHistoryLen);
+    if (int rc = copy_d2h(ring.data(), c->a.history + (int64_t)run * kHistoryLen, sizeof(double) * kHistoryLen))
+        return rc;
+    const int64_t cnt = std::min<int64_t>(step, kHistoryLen);
+    for (int64_t j = 0; j < cnt; ++j) h_out[j] = ring[(step - cnt + j) % kHistoryLen];
+    *n = cnt;
+    return SLPIC_OK;
+}
+
 static int cur_buffer(Context* c, int* b) {
     HIP_TRY(hipDeviceSynchronize());
     return copy_d2h(b, c->a.cur, sizeof(int));

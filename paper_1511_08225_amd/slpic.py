@@ -90,6 +90,7 @@ def lib():
             "slpic_step": (ctypes.c_int, [_P, i32, _P]),
             "slpic_moments": (ctypes.c_int, [_P, i32, _P, _P]),
             "slpic_moments_sample": (ctypes.c_int, [_P, i32, _P]),
+            "slpic_wall_history": (ctypes.c_int, [_P, i32, _PD, _PI64]),
             "slpic_mlp_act_bytes": (ctypes.c_size_t, [i32]),
             "slpic_mlp_work_bytes": (ctypes.c_size_t, [i32]),
             "slpic_mlp_to_bf16": (ctypes.c_int, [_P, _P, _P]),
@@ -292,6 +293,13 @@ class Sim:
         _check(lib().slpic_moments_window(self._ctx, run, _P(out.data_ptr()), int(bool(reset)), self._stream()),
                "slpic_moments_window")
         return out
+
+    def wall_history(self, run: int = 0) -> np.ndarray:
+        """Phi_w after each of the run's last min(step, 4096) steps, oldest first."""
+        out = np.zeros(4096)
+        n = ctypes.c_int64(0)
+        _check(lib().slpic_wall_history(self._ctx, run, _dp(out), ctypes.byref(n)), "slpic_wall_history")
+        return out[:n.value].copy()
 
     def wall_potential(self, run: int = 0) -> float:
         return self.status(run)["wall_potential"]
