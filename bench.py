@@ -65,11 +65,14 @@ def traffic_probe(args) -> int:
     torch.cuda.synchronize()
     del src, dst
     torch.cuda.empty_cache()
-    cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc, sort_every=args.sort_every)
-    sim = slpic.Sim(cfg, precision=args.precision, sort_every=args.sort_every, chunk=args.chunk, graph_steps=0)
+    cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc)
+    params = launch_params(cfg, args)
+    sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
+                    chunk=params["chunk"], block=params["block"], graph_steps=0)
     sim.step(args.steps)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "traffic", "steps": args.steps, "pushed": sim.pushed_total()}), flush=True)
+    print(json.dumps({"probe": "traffic", "steps": args.steps, "pushed": sim.pushed_total(), "launch": params}),
+          flush=True)
     sim.close()
     return 0
 
@@ -343,11 +346,23 @@ def warm_bench(args) -> int:
     return 0
 
 
-def run_timed(cfg, args, steps, warmup):
+def launch_params(cfg, args) -> dict:
+    """Push chunk, workgroup size, sort period and bucket: from the autotuner
+    (cached per workload signature) unless given on the command line."""
+    from paper_1511_08225_amd import autotune
+    if args.no_tune:
+        return {"chunk": args.chunk, "block": 128, "sort_every": args.sort_every, "sort_bucket": 1}
+    return autotune.tune([cfg], args.precision, log=lambda m: print(m, file=sys.stderr, flush=True))
+
+
+def run_timed(cfg, args, steps, warmup, params):
     import torch
     from paper_1511_08225_amd import slpic
-    sim = slpic.Sim(cfg, precision=args.precision, sort_every=args.sort_every, chunk=args.chunk,
-                    graph_steps=args.graph_steps)
+    g = max(16, params["sort_every"])
+    steps = max(g, (steps // g) * g)
+    warmup = max(g, (warmup // g) * g)
+    sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"],
+                    sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"], graph_steps=g)
     sim.step(warmup)
     torch.cuda.synchronize()
     sim.profile(True)  # events around each push launch
@@ -361,7 +376,7 @@ def run_timed(cfg, args, steps, warmup):
     prof = sim.profile_read()["push"]
     st = sim.status(0)
     sim.close()
-    return pushes, t1 - t0, prof, st
+    return pushes, t1 - t0, prof, st, steps, warmup
 
 
 def main() -> int:
@@ -372,8 +387,8 @@ def main() -> int:
     ap.add_argument("--u", type=float, default=2.0, help="speed limit in ion thermal speeds (inf = PIC)")
     ap.add_argument("--ppc", type=int, default=1000)
     ap.add_argument("--sort-every", type=int, default=16)
-    ap.add_argument("--graph-steps", type=int, default=16)
-    ap.add_argument("--chunk", type=int, default=512, help="slots per push wavefront")
+    ap.add_argument("--chunk", type=int, default=512, help="slots per push wavefront (with --no-tune)")
+    ap.add_argument("--no-tune", action="store_true", help="use --chunk/--sort-every instead of the autotuner")
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-variant", action="store_true")
@@ -393,7 +408,9 @@ def main() -> int:
                     help="turn two rocprofv3 counter files into the per-launch traffic record and exit")
     args = ap.parse_args()
     if args.traffic_from:
-        return traffic_from(args.traffic_from[0], args.traffic_from[1], args.ppc, args.chunk)
+        import workloads
+        chunk = launch_params(workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc), args)["chunk"]
+        return traffic_from(args.traffic_from[0], args.traffic_from[1], args.ppc, chunk)
     if args.traffic_probe:
         return traffic_probe(args)
     if args.sweep:
@@ -405,19 +422,17 @@ def main() -> int:
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
-    g = args.graph_steps
-    steps = max(g, (args.steps // g) * g) if g else args.steps
-    warmup = (args.warmup // g) * g if g else args.warmup
 
     import workloads
-    cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc, sort_every=args.sort_every)
-    pushes, elapsed, prof, st = run_timed(cfg, args, steps, warmup)
+    cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc)
+    params = launch_params(cfg, args)
+    pushes, elapsed, prof, st, steps, warmup = run_timed(cfg, args, args.steps, args.warmup, params)
     bpp = BYTES_PER_PUSH[args.precision]
     launches = max(prof["launches"], 1)
     push_ms = prof["ms"] / launches
     bytes_per_launch = bpp * pushes / launches
     achieved = bytes_per_launch / (push_ms * 1e-3) / 1e9
-    traffic = traffic_for(args.ppc, args.chunk)
+    traffic = traffic_for(args.ppc, params["chunk"])
     line = {
         "metric": METRIC,
         "value": pushes / elapsed,
@@ -434,10 +449,11 @@ def main() -> int:
         "config": {
             "workload": (f"1D3V argon sheath, 2048 cells over 1024 Debye lengths, {args.ppc} particles/cell/"
                          f"species ({2 * 2048 * args.ppc} particles at load), Te/Ti=20, u={args.u} v_ti, "
-                         f"dt={cfg['dt']:.4g}/omega_pe, cell sort every {args.sort_every} steps"),
+                         f"dt={cfg['dt']:.4g}/omega_pe, cell sort every {params['sort_every']} steps"),
             "particles": 2 * 2048 * args.ppc,
             "u_over_vti": args.u,
             "dt": cfg["dt"],
+            "launch": params,
         },
         "roofline": {
             "bound": "hbm",
@@ -457,15 +473,16 @@ def main() -> int:
     if not args.no_hbm_variant and args.ppc == 1000:
         # the same sheath with 10x the particles per cell (41M particles,
         # 655 MB of particle state: larger than the 256 MB Infinity Cache)
-        cfg10 = workloads.production_sheath(u_over_vti=args.u, ppc=10 * args.ppc, sort_every=args.sort_every)
-        p10, e10, prof10, _ = run_timed(cfg10, args, 4 * g if g else 64, g if g else 16)
+        cfg10 = workloads.production_sheath(u_over_vti=args.u, ppc=10 * args.ppc)
+        params10 = launch_params(cfg10, args)
+        p10, e10, prof10, _, s10, _ = run_timed(cfg10, args, 256, 64, params10)
         l10 = max(prof10["launches"], 1)
         ms10 = prof10["ms"] / l10
         a10 = bpp * p10 / l10 / (ms10 * 1e-3) / 1e9
-        line["hbm_variant"] = {"particles": 2 * 2048 * 10 * args.ppc, "value": p10 / e10,
-                               "push_avg_launch_ms": ms10, "achieved_GBs": a10,
-                               "frac": a10 / HBM_PEAK_GBS,
-                               "traffic": traffic_for(10 * args.ppc, args.chunk)}
+        line["hbm_variant"] = {"particles": 2 * 2048 * 10 * args.ppc, "value": p10 / e10, "steps": s10,
+                               "launch": params10, "push_avg_launch_ms": ms10, "achieved_GBs": a10,
+                               "frac": a10 / HBM_PEAK_GBS, "bound": "hbm", "peak": HBM_PEAK_GBS,
+                               "traffic": traffic_for(10 * args.ppc, params10["chunk"])}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

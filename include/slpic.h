@@ -104,7 +104,8 @@ typedef struct {
     int32_t precision;    /* SLPIC_F32 / SLPIC_F64 (all runs of a context)          */
     int32_t sort_every;   /* stable cell sort + compaction every k steps; 0 = never  */
     int32_t sort_bucket;  /* sort key = cell / bucket; 0 = compaction only (key 0)   */
-    int32_t chunk;        /* particles per push workgroup; 0 = default               */
+    int32_t chunk;        /* particles per push wavefront: 64 P, P in {1, 2, 4, 8,  */
+                          /* 16}; 0 = default (512 for F32, 256 for F64)             */
     int32_t block;        /* threads per push workgroup: 64, 128, 192 or 256, one   */
                           /* wavefront per chunk; 0 = default (128)                  */
     int32_t graph_steps;  /* steps captured per HIP graph; 0 = direct launches       */

@@ -186,9 +186,9 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
     if (t.sort_tile == 0) t.sort_tile = 16384;
     if (t.block < 64 || t.block > 256 || t.block % 64) return SLPIC_EINVAL;  // 1..4 push waves
-    {   // one wavefront per push chunk: chunk = 64 * P, P in {1, 2, 4, 8}
+    {   // one wavefront per push chunk: chunk = 64 * P, P in {1, 2, 4, 8, 16}
         const int per = t.chunk / 64;
-        if (t.chunk % 64 || (per != 1 && per != 2 && per != 4 && per != 8)) return SLPIC_EINVAL;
+        if (t.chunk % 64 || (per != 1 && per != 2 && per != 4 && per != 8 && per != 16)) return SLPIC_EINVAL;
     }
     if (t.sort_every > 0 && t.graph_steps > 0 && t.graph_steps % t.sort_every)
         t.graph_steps = (t.graph_steps / t.sort_every + 1) * t.sort_every;

@@ -35,7 +35,9 @@ def test_coordinate_descent_finds_separable_optimum_and_caches(tmp_path):
     cache = json.load(open(path))
     key = autotune.signature(cfgs, "f32")
     assert cache[key]["params"] == opt
-    assert len(cache[key]["trials"]) == 1 + (2 * 3 - 1) + (4 - 1) + (3 - 1)
+    nc = len(autotune.CANDIDATES["chunk"]) * len(autotune.CANDIDATES["block"])
+    # the default, its (chunk, block) group, then one new trial per other value
+    assert len(cache[key]["trials"]) == 1 + (nc - 1) + (4 - 1) + (3 - 1)
     # a cached key is returned without measuring
     def boom(*a):
         raise AssertionError("measured a cached signature")
