@@ -119,6 +119,25 @@ def lib():
                                          _PD]),
             "orc_steady_init": (None, [ctypes.POINTER(_Steady), ctypes.c_int32, _D]),
             "orc_steady_feed": (None, [ctypes.POINTER(_Steady), _D, _I64]),
+            "orc2_create": (_VP, [ctypes.POINTER(_Config), _I32, _I32]),
+            "orc2_destroy": (None, [_VP]),
+            "orc2_load": (None, [_VP]),
+            "orc2_step": (None, [_VP, _I32]),
+            "orc2_sort": (None, [_VP, _PI32, _PI32]),
+            "orc2_refresh_fields": (None, [_VP]),
+            "orc2_poisson": (None, [_I32, _I32, _D, _PD, _PD, _PD, _PD]),
+            "orc2_load_particle": (None, [ctypes.POINTER(_Config), _I32, _I32, ctypes.c_uint32, _PD]),
+            "orc2_inject_particle": (None, [ctypes.POINTER(_Config), _I32, _I32, ctypes.c_uint32,
+                                            ctypes.c_uint32, _PD]),
+            "orc2_sort_key": (_I64, [_I32, _I32, _D, _D]),
+            "orc2_nslots": (_I64, [_VP, _I32]),
+            "orc2_step_index": (_I64, [_VP]),
+            "orc2_acc_e": (_D, [_VP]),
+            "orc2_weight": (_D, [_VP, _I32]),
+            "orc2_get_particles": (None, [_VP, _I32, _PD, _PD, _PD, _PD, _PD]),
+            "orc2_set_particles": (None, [_VP, _I32, _I64, _PD, _PD, _PD, _PD, _PD]),
+            "orc2_set_counters": (None, [_VP, _I64, _D]),
+            "orc2_get_grid": (None, [_VP, _PD, _PD, _PD, _PD, _PD]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -368,6 +387,107 @@ class Run:
 
     def weights(self):
         return [weight(self.cfg, s) for s in range(self.nspecies)]
+
+
+# ------------------------------------------------------------------- 2D3V
+def poisson2d(nx: int, ny: int, dx: float, Q: np.ndarray):
+    """phi, Ex, Ey on the (nx+1, ny) nodes from the node charge Q (dy = dx)."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    assert Q.shape == (nx + 1, ny)
+    phi, Ex, Ey = (np.zeros((nx + 1, ny)) for _ in range(3))
+    lib().orc2_poisson(nx, ny, dx, _dp(Q), _dp(phi), _dp(Ex), _dp(Ey))
+    return phi, Ex, Ey
+
+
+def load_particle2d(cfg: dict, ny: int, s: int, i: int) -> np.ndarray:
+    """(x, y, vx, vy, vz) of load slot i."""
+    c = make_config(cfg)
+    out = np.zeros(5)
+    lib().orc2_load_particle(ctypes.byref(c), ny, s, i, _dp(out))
+    return out
+
+
+def inject_particle2d(cfg: dict, ny: int, s: int, k: int, step: int) -> np.ndarray:
+    c = make_config(cfg)
+    out = np.zeros(5)
+    lib().orc2_inject_particle(ctypes.byref(c), ny, s, k, step, _dp(out))
+    return out
+
+
+def sort_key2d(ny: int, tile: int, x: float, y: float) -> int:
+    return lib().orc2_sort_key(ny, tile, x, y)
+
+
+class Run2D:
+    """One 2D3V SLPIC run on the CPU (FP64): x as in 1D, y periodic in
+    [0, ny) cells, dy = dx; nodes (i, j) at i*ny + j."""
+
+    def __init__(self, cfg: dict, ny: int, tile: int = 1, load: bool = True):
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        self.nx, self.ny, self.tile = self._c.nx, int(ny), int(tile)
+        self._h = lib().orc2_create(ctypes.byref(self._c), self.ny, self.tile)
+        if load:
+            lib().orc2_load(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.orc2_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def step(self, n: int = 1):
+        lib().orc2_step(self._h, n)
+
+    def refresh_fields(self):
+        lib().orc2_refresh_fields(self._h)
+
+    def sort(self):
+        n_before = [self.nslots(s) for s in range(2)]
+        perms = [np.zeros(max(1, n), dtype=np.int32) for n in n_before]
+        lib().orc2_sort(self._h, perms[0].ctypes.data_as(_PI32), perms[1].ctypes.data_as(_PI32))
+        return [perms[s][: self.nslots(s)] for s in range(2)]
+
+    def nslots(self, s: int) -> int:
+        return lib().orc2_nslots(self._h, s)
+
+    @property
+    def step_index(self) -> int:
+        return lib().orc2_step_index(self._h)
+
+    @property
+    def acc_e(self) -> float:
+        return lib().orc2_acc_e(self._h)
+
+    def weight(self, s: int) -> float:
+        return lib().orc2_weight(self._h, s)
+
+    def particles(self, s: int):
+        """(x, y, vx, vy, vz) in grid units / velocity units; dead slots x = -1."""
+        n = self.nslots(s)
+        arrs = [np.zeros(max(1, n)) for _ in range(5)]
+        lib().orc2_get_particles(self._h, s, *[_dp(a) for a in arrs])
+        return tuple(a[:n] for a in arrs)
+
+    def set_particles(self, s: int, x, y, vx, vy, vz):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, vx, vy, vz)]
+        lib().orc2_set_particles(self._h, s, len(arrs[0]), *[_dp(a) for a in arrs])
+
+    def set_counters(self, step: int, acc_e: float):
+        lib().orc2_set_counters(self._h, step, acc_e)
+
+    def grid(self):
+        shape = (self.nx + 1, self.ny)
+        Q0, Q1, phi, Ex, Ey = (np.zeros(shape) for _ in range(5))
+        lib().orc2_get_grid(self._h, *[_dp(a) for a in (Q0, Q1, phi, Ex, Ey)])
+        return {"Q": np.stack([Q0, Q1]), "phi": phi, "Ex": Ex, "Ey": Ey}
+
+    def wall_potential(self) -> float:
+        """Phi_w: the y-mean of phi at x = 0 (phi = 0 at the wall)."""
+        return float(self.grid()["phi"][0].mean())
 
 
 def thermal_speed(cfg: dict, s: int) -> float:

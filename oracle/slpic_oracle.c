@@ -905,3 +905,375 @@ void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double*
 }
 
 void orc_get_steady(const orc_run* r, orc_steady* out) { *out = r->steady; }
+
+/* ======================================================================== */
+/* 2D3V: x in [0, nx) with the symmetry plane at x = 0 and the grounded     */
+/* absorbing wall at x = nx (as in 1D), y periodic in [0, ny); dy = dx.      */
+/* Nodes (i, j), i = 0..nx, j = 0..ny-1, stored at i*ny + j.  E lies in the  */
+/* (x, y) plane, so v_z is a constant of the motion.                          */
+/* ======================================================================== */
+struct orc2_run {
+    orc_config cfg;
+    int32_t ny, tile; /* sort key: the tile x tile block of cells holding the particle */
+    double w[2], qw[2], qm[2];
+    int64_t n[2], cap[2];
+    double *x[2], *y[2], *vx[2], *vy[2], *vz[2];
+    double *Q[2], *phi, *Ex, *Ey;
+    double acc_e;
+    int64_t step;
+    int64_t absorbed_total[2], injected_total[2];
+};
+
+static void ensure2(orc2_run* r, int s, int64_t need) {
+    if (need <= r->cap[s]) return;
+    int64_t cap = r->cap[s] > 0 ? r->cap[s] : 16;
+    while (cap < need) cap *= 2;
+    double** arrs[5] = {&r->x[s], &r->y[s], &r->vx[s], &r->vy[s], &r->vz[s]};
+    for (int k = 0; k < 5; ++k) *arrs[k] = (double*)realloc(*arrs[k], sizeof(double) * (size_t)cap);
+    r->cap[s] = cap;
+}
+
+orc2_run* orc2_create(const orc_config* cfg, int32_t ny, int32_t tile) {
+    orc2_run* r = (orc2_run*)calloc(1, sizeof(orc2_run));
+    r->cfg = *cfg;
+    r->ny = ny;
+    r->tile = tile > 0 ? tile : 1;
+    size_t nodes = (size_t)(cfg->nx + 1) * (size_t)ny;
+    for (int s = 0; s < cfg->nspecies; ++s) {
+        /* weight: dx dy Z / ppc, the 2D cell area holding ppc g-particles */
+        r->w[s] = orc_weight(cfg, s) * cfg->dx;
+        r->qw[s] = cfg->species[s].charge * r->w[s];
+        r->qm[s] = cfg->species[s].charge / cfg->species[s].mass;
+        r->Q[s] = (double*)calloc(nodes, sizeof(double));
+    }
+    r->phi = (double*)calloc(nodes, sizeof(double));
+    r->Ex = (double*)calloc(nodes, sizeof(double));
+    r->Ey = (double*)calloc(nodes, sizeof(double));
+    return r;
+}
+
+void orc2_destroy(orc2_run* r) {
+    if (!r) return;
+    for (int s = 0; s < 2; ++s) {
+        free(r->x[s]); free(r->y[s]); free(r->vx[s]); free(r->vy[s]); free(r->vz[s]); free(r->Q[s]);
+    }
+    free(r->phi); free(r->Ex); free(r->Ey);
+    free(r);
+}
+
+/* Cold load in 2D: x = nx U, y = ny U, then the velocity draws of the 1D
+ * loader (g = f/beta, Eq. 5). */
+void orc2_load_particle(const orc_config* cfg, int32_t ny, int s, uint32_t i, double out[5]) {
+    orc_stream st;
+    stream_init(&st, cfg, i, 0u, ORC_PURPOSE_LOAD, s);
+    double vt = species_vt(cfg, s);
+    out[0] = (double)cfg->nx * stream_next(&st);
+    if (out[0] >= (double)cfg->nx) out[0] = nextafter((double)cfg->nx, 0.0);
+    out[1] = (double)ny * stream_next(&st);
+    if (out[1] >= (double)ny) out[1] = nextafter((double)ny, 0.0);
+    if (isinf(cfg->u)) {
+        double z[3];
+        stream_normal3(&st, z);
+        out[2] = vt * z[0]; out[3] = vt * z[1]; out[4] = vt * z[2];
+        return;
+    }
+    double sp = sample_g_speed(&st, cfg->beta_kind, cfg->u / vt);
+    double mu = 2.0 * stream_next(&st) - 1.0;
+    double ph = TWO_PI * stream_next(&st);
+    double sn = sqrt(fmax(0.0, 1.0 - mu * mu));
+    out[2] = vt * sp * mu;
+    out[3] = vt * sp * (sn * cos(ph));
+    out[4] = vt * sp * (sn * sin(ph));
+}
+
+void orc2_inject_particle(const orc_config* cfg, int32_t ny, int s, uint32_t k, uint32_t step, double out[5]) {
+    orc_stream st;
+    stream_init(&st, cfg, k, step, ORC_PURPOSE_INJECT, s);
+    double vt = species_vt(cfg, s);
+    out[0] = (double)cfg->source_cells * stream_next(&st);
+    if (out[0] >= (double)cfg->source_cells) out[0] = nextafter((double)cfg->source_cells, 0.0);
+    out[1] = (double)ny * stream_next(&st);
+    if (out[1] >= (double)ny) out[1] = nextafter((double)ny, 0.0);
+    double z[3];
+    stream_normal3(&st, z);
+    out[2] = vt * z[0]; out[3] = vt * z[1]; out[4] = vt * z[2];
+}
+
+/* Poisson in 2D, eps0 = 1: -lap phi = rho = Q/dV (dV = dx dy, half at the x
+ * end nodes).  A discrete Fourier transform in y (periodic) turns the
+ * five-point stencil into, per mode m, the 1D three-point system of
+ * orc_poisson1d plus kappa_m phi with kappa_m = (4/dy^2) sin^2(pi m/ny);
+ * node 0 symmetric, phi = 0 at node nx; Thomas per mode (real and imaginary
+ * parts separately), inverse transform.  E = -grad phi by centred
+ * differences (periodic in y; in x: E_x = 0 at node 0, the one-sided
+ * second-order difference at the wall). */
+void orc2_poisson(int32_t nx, int32_t ny, double dx, const double* Q, double* phi, double* Ex, double* Ey) {
+    int nodes_x = nx + 1;
+    double* re = (double*)calloc((size_t)nodes_x * ny, sizeof(double));
+    double* im = (double*)calloc((size_t)nodes_x * ny, sizeof(double));
+    for (int i = 0; i < nodes_x; ++i) {
+        double dV = (i == 0 || i == nx) ? 0.5 * dx * dx : dx * dx;
+        for (int m = 0; m < ny; ++m) {
+            double sr = 0.0, si = 0.0;
+            for (int j = 0; j < ny; ++j) {
+                double ang = TWO_PI * (double)((int64_t)m * j % ny) / (double)ny;
+                double rho = Q[(size_t)i * ny + j] / dV;
+                sr += rho * cos(ang);
+                si -= rho * sin(ang);
+            }
+            re[(size_t)i * ny + m] = sr;
+            im[(size_t)i * ny + m] = si;
+        }
+    }
+    double* cp = (double*)malloc(sizeof(double) * nx);
+    double* dpr = (double*)malloc(sizeof(double) * nx);
+    double* dpi = (double*)malloc(sizeof(double) * nx);
+    double dx2 = dx * dx;
+    for (int m = 0; m < ny; ++m) {
+        double sm = sin(0.5 * TWO_PI * (double)m / (double)ny);
+        double kd = 4.0 * sm * sm; /* kappa_m dx^2 with dy = dx */
+        for (int i = 0; i < nx; ++i) {
+            double a = (i == 0) ? 0.0 : -1.0, b = 2.0 + kd, c = (i == 0) ? -2.0 : -1.0;
+            double rr = re[(size_t)i * ny + m] * dx2, ri = im[(size_t)i * ny + m] * dx2;
+            if (i == 0) {
+                cp[0] = c / b; dpr[0] = rr / b; dpi[0] = ri / b;
+            } else {
+                double den = b - a * cp[i - 1];
+                cp[i] = c / den;
+                dpr[i] = (rr - a * dpr[i - 1]) / den;
+                dpi[i] = (ri - a * dpi[i - 1]) / den;
+            }
+        }
+        re[(size_t)nx * ny + m] = 0.0;
+        im[(size_t)nx * ny + m] = 0.0;
+        re[(size_t)(nx - 1) * ny + m] = dpr[nx - 1];
+        im[(size_t)(nx - 1) * ny + m] = dpi[nx - 1];
+        for (int i = nx - 2; i >= 0; --i) {
+            re[(size_t)i * ny + m] = dpr[i] - cp[i] * re[(size_t)(i + 1) * ny + m];
+            im[(size_t)i * ny + m] = dpi[i] - cp[i] * im[(size_t)(i + 1) * ny + m];
+        }
+    }
+    for (int i = 0; i < nodes_x; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < ny; ++m) {
+                double ang = TWO_PI * (double)((int64_t)m * j % ny) / (double)ny;
+                s += re[(size_t)i * ny + m] * cos(ang) - im[(size_t)i * ny + m] * sin(ang);
+            }
+            phi[(size_t)i * ny + j] = (i == nx) ? 0.0 : s / (double)ny;
+        }
+    for (int i = 0; i < nodes_x; ++i)
+        for (int j = 0; j < ny; ++j) {
+            const double* p = phi;
+            size_t o = (size_t)i * ny + j;
+            if (i == 0) Ex[o] = 0.0;
+            else if (i < nx) Ex[o] = -(p[o + ny] - p[o - ny]) / (2.0 * dx);
+            else Ex[o] = -(3.0 * p[o] - 4.0 * p[o - ny] + p[o - 2 * (size_t)ny]) / (2.0 * dx);
+            int jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+            Ey[o] = -(p[(size_t)i * ny + jp] - p[(size_t)i * ny + jm]) / (2.0 * dx);
+        }
+    free(re); free(im); free(cp); free(dpr); free(dpi);
+}
+
+/* beta-weighted bilinear (2D CIC) deposit of both species. */
+static void deposit2(orc2_run* r) {
+    int ny = r->ny;
+    size_t nodes = (size_t)(r->cfg.nx + 1) * ny;
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        memset(r->Q[s], 0, sizeof(double) * nodes);
+        for (int64_t i = 0; i < r->n[s]; ++i) {
+            double xt = r->x[s][i];
+            if (xt < 0.0) continue;
+            double yt = r->y[s][i];
+            double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+            double wb = r->qw[s] * beta_of_s2(r->cfg.beta_kind, r->cfg.u, norm2(v));
+            int cx = (int)floor(xt), cy = (int)floor(yt);
+            double fx = xt - cx, fy = yt - cy;
+            int cy1 = (cy + 1) % ny;
+            r->Q[s][(size_t)cx * ny + cy] += wb * (1.0 - fx) * (1.0 - fy);
+            r->Q[s][(size_t)(cx + 1) * ny + cy] += wb * fx * (1.0 - fy);
+            r->Q[s][(size_t)cx * ny + cy1] += wb * (1.0 - fx) * fy;
+            r->Q[s][(size_t)(cx + 1) * ny + cy1] += wb * fx * fy;
+        }
+    }
+}
+
+static void solve2(orc2_run* r) {
+    size_t nodes = (size_t)(r->cfg.nx + 1) * r->ny;
+    double* Qt = (double*)calloc(nodes, sizeof(double));
+    for (size_t k = 0; k < nodes; ++k)
+        for (int s = 0; s < r->cfg.nspecies; ++s) Qt[k] += r->Q[s][k];
+    orc2_poisson(r->cfg.nx, r->ny, r->cfg.dx, Qt, r->phi, r->Ex, r->Ey);
+    free(Qt);
+}
+
+void orc2_refresh_fields(orc2_run* r) {
+    deposit2(r);
+    solve2(r);
+}
+
+/* Stable counting sort by the block of tile x tile cells holding each
+ * particle, blocks numbered x-major: key = (cx/tile) * nty + cy/tile with
+ * nty = ceil(ny/tile) (tile = 1: the cell index cx*ny + cy).  Dead slots are
+ * dropped; perm (new slot -> old slot) when given. */
+int64_t orc2_sort_key(int32_t ny, int32_t tile, double x, double y) {
+    if (x < 0.0) return -1;
+    int64_t nty = (ny + tile - 1) / tile;
+    return ((int64_t)floor(x) / tile) * nty + (int64_t)floor(y) / tile;
+}
+
+void orc2_sort(orc2_run* r, int32_t* perm0, int32_t* perm1) {
+    int ny = r->ny, T = r->tile;
+    int64_t nkeys = (int64_t)((r->cfg.nx + T - 1) / T) * ((ny + T - 1) / T);
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        int64_t n = r->n[s];
+        int64_t* keys = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t* start = (int64_t*)calloc((size_t)nkeys + 1, sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i) {
+            keys[i] = orc2_sort_key(ny, T, r->x[s][i], r->y[s][i]);
+            if (keys[i] >= 0) start[keys[i] + 1] += 1;
+        }
+        for (int64_t k = 0; k < nkeys; ++k) start[k + 1] += start[k];
+        int64_t nlive = start[nkeys];
+        double* tmp[5];
+        double* src[5] = {r->x[s], r->y[s], r->vx[s], r->vy[s], r->vz[s]};
+        for (int a = 0; a < 5; ++a) tmp[a] = (double*)malloc(sizeof(double) * (size_t)(nlive + 1));
+        int32_t* perm = (s == 0) ? perm0 : perm1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (keys[i] < 0) continue;
+            int64_t d = start[keys[i]]++;
+            for (int a = 0; a < 5; ++a) tmp[a][d] = src[a][i];
+            if (perm) perm[d] = (int32_t)i;
+        }
+        for (int a = 0; a < 5; ++a) {
+            memcpy(src[a], tmp[a], sizeof(double) * (size_t)nlive);
+            free(tmp[a]);
+        }
+        r->n[s] = nlive;
+        free(keys); free(start);
+    }
+}
+
+void orc2_load(orc2_run* r) {
+    int64_t cells = (int64_t)r->cfg.nx * r->ny;
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        int64_t n0 = cells * r->cfg.species[s].ppc;
+        ensure2(r, s, n0);
+        for (int64_t i = 0; i < n0; ++i) {
+            double p[5];
+            orc2_load_particle(&r->cfg, r->ny, s, (uint32_t)i, p);
+            r->x[s][i] = p[0]; r->y[s][i] = p[1]; r->vx[s][i] = p[2]; r->vy[s][i] = p[3]; r->vz[s][i] = p[4];
+        }
+        r->n[s] = n0;
+    }
+    r->step = 0;
+    r->acc_e = 0.0;
+    if (r->cfg.sort_every > 0) orc2_sort(r, NULL, NULL);
+    orc2_refresh_fields(r);
+}
+
+static void inject2(orc2_run* r, int s, int64_t count) {
+    ensure2(r, s, r->n[s] + count);
+    for (int64_t k = 0; k < count; ++k) {
+        double p[5];
+        orc2_inject_particle(&r->cfg, r->ny, s, (uint32_t)k, (uint32_t)r->step, p);
+        int64_t i = r->n[s] + k;
+        r->x[s][i] = p[0]; r->y[s][i] = p[1]; r->vx[s][i] = p[2]; r->vy[s][i] = p[3]; r->vz[s][i] = p[4];
+    }
+    r->n[s] += count;
+    r->injected_total[s] += count;
+}
+
+/* One step of App. Eq. (A2) in 2D: bilinear gather of E^n(x^n), the exact
+ * velocity map with a = (q/m)(E_x, E_y, 0) frozen, x += beta vx dt/dx,
+ * y += beta vy dt/dy (periodic), the walls in x, source, deposit, solve. */
+void orc2_step(orc2_run* r, int32_t nsteps) {
+    const orc_config* cfg = &r->cfg;
+    int ny = r->ny;
+    double dtdx = cfg->dt / cfg->dx;
+    for (int32_t it = 0; it < nsteps; ++it) {
+        int64_t absorbed[2] = {0, 0};
+        for (int s = 0; s < cfg->nspecies; ++s) {
+            for (int64_t i = 0; i < r->n[s]; ++i) {
+                double xt = r->x[s][i];
+                if (xt < 0.0) continue;
+                double yt = r->y[s][i];
+                int cx = (int)floor(xt), cy = (int)floor(yt);
+                double fx = xt - cx, fy = yt - cy;
+                int cy1 = (cy + 1) % ny;
+                size_t o00 = (size_t)cx * ny + cy, o10 = (size_t)(cx + 1) * ny + cy;
+                size_t o01 = (size_t)cx * ny + cy1, o11 = (size_t)(cx + 1) * ny + cy1;
+                double w00 = (1.0 - fx) * (1.0 - fy), w10 = fx * (1.0 - fy), w01 = (1.0 - fx) * fy, w11 = fx * fy;
+                double ex = r->Ex[o00] * w00 + r->Ex[o10] * w10 + r->Ex[o01] * w01 + r->Ex[o11] * w11;
+                double ey = r->Ey[o00] * w00 + r->Ey[o10] * w10 + r->Ey[o01] * w01 + r->Ey[o11] * w11;
+                double a[3] = {r->qm[s] * ex, r->qm[s] * ey, 0.0};
+                double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+                double v1[3];
+                orc_kick_exact(cfg->beta_kind, cfg->u, cfg->dt, v, a, v1);
+                double b = beta_of_s2(cfg->beta_kind, cfg->u, norm2(v1));
+                double xn = xt + b * v1[0] * dtdx;
+                double yn = yt + b * v1[1] * dtdx;
+                if (yn < 0.0) yn += (double)ny;
+                else if (yn >= (double)ny) yn -= (double)ny;
+                if (yn >= (double)ny) yn = 0.0; /* -0 rounded onto ny */
+                if (xn < 0.0) {
+                    xn = -xn;
+                    v1[0] = -v1[0];
+                }
+                r->vx[s][i] = v1[0];
+                r->vy[s][i] = v1[1];
+                r->vz[s][i] = v1[2];
+                if (xn >= (double)cfg->nx) {
+                    r->x[s][i] = -1.0;
+                    absorbed[s] += 1;
+                } else {
+                    r->x[s][i] = xn;
+                    r->y[s][i] = yn;
+                }
+            }
+            r->absorbed_total[s] += absorbed[s];
+        }
+        if (cfg->nspecies == 2) {
+            int64_t ni = absorbed[1];
+            r->acc_e += (double)ni * (r->w[1] / r->w[0]);
+            int64_t ne = (int64_t)floor(r->acc_e);
+            r->acc_e -= (double)ne;
+            inject2(r, 1, ni);
+            inject2(r, 0, ne);
+        }
+        deposit2(r);
+        solve2(r);
+        r->step += 1;
+        if (cfg->sort_every > 0 && r->step % cfg->sort_every == 0) orc2_sort(r, NULL, NULL);
+    }
+}
+
+int64_t orc2_nslots(const orc2_run* r, int32_t s) { return r->n[s]; }
+int64_t orc2_step_index(const orc2_run* r) { return r->step; }
+double orc2_acc_e(const orc2_run* r) { return r->acc_e; }
+double orc2_weight(const orc2_run* r, int32_t s) { return r->w[s]; }
+void orc2_get_particles(const orc2_run* r, int32_t s, double* x, double* y, double* vx, double* vy, double* vz) {
+    size_t b = sizeof(double) * (size_t)r->n[s];
+    memcpy(x, r->x[s], b); memcpy(y, r->y[s], b); memcpy(vx, r->vx[s], b); memcpy(vy, r->vy[s], b);
+    memcpy(vz, r->vz[s], b);
+}
+void orc2_set_particles(orc2_run* r, int32_t s, int64_t n, const double* x, const double* y, const double* vx,
+                        const double* vy, const double* vz) {
+    ensure2(r, s, n);
+    size_t b = sizeof(double) * (size_t)n;
+    memcpy(r->x[s], x, b); memcpy(r->y[s], y, b); memcpy(r->vx[s], vx, b); memcpy(r->vy[s], vy, b);
+    memcpy(r->vz[s], vz, b);
+    r->n[s] = n;
+}
+void orc2_set_counters(orc2_run* r, int64_t step, double acc_e) {
+    r->step = step;
+    r->acc_e = acc_e;
+}
+void orc2_get_grid(const orc2_run* r, double* Q0, double* Q1, double* phi, double* Ex, double* Ey) {
+    size_t b = sizeof(double) * (size_t)(r->cfg.nx + 1) * r->ny;
+    if (Q0) memcpy(Q0, r->Q[0], b);
+    if (Q1) memcpy(Q1, r->Q[1], b);
+    if (phi) memcpy(phi, r->phi, b);
+    if (Ex) memcpy(Ex, r->Ex, b);
+    if (Ey) memcpy(Ey, r->Ey, b);
+}

@@ -131,6 +131,28 @@ void orc_set_counters(orc_run* r, int64_t step, double acc_e);
 void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E);
 void orc_get_steady(const orc_run* r, orc_steady* out);
 
+/* 2D3V (y periodic, dy = dx): nodes (i, j) at i*ny + j, i = 0..nx. */
+typedef struct orc2_run orc2_run;
+orc2_run* orc2_create(const orc_config* cfg, int32_t ny, int32_t tile);
+int64_t orc2_sort_key(int32_t ny, int32_t tile, double x, double y);
+void orc2_destroy(orc2_run* r);
+void orc2_load(orc2_run* r);
+void orc2_step(orc2_run* r, int32_t nsteps);
+void orc2_sort(orc2_run* r, int32_t* perm0, int32_t* perm1);
+void orc2_refresh_fields(orc2_run* r);
+void orc2_poisson(int32_t nx, int32_t ny, double dx, const double* Q, double* phi, double* Ex, double* Ey);
+void orc2_load_particle(const orc_config* cfg, int32_t ny, int s, uint32_t i, double out[5]);
+void orc2_inject_particle(const orc_config* cfg, int32_t ny, int s, uint32_t k, uint32_t step, double out[5]);
+int64_t orc2_nslots(const orc2_run* r, int32_t s);
+int64_t orc2_step_index(const orc2_run* r);
+double orc2_acc_e(const orc2_run* r);
+double orc2_weight(const orc2_run* r, int32_t s);
+void orc2_get_particles(const orc2_run* r, int32_t s, double* x, double* y, double* vx, double* vy, double* vz);
+void orc2_set_particles(orc2_run* r, int32_t s, int64_t n, const double* x, const double* y, const double* vx,
+                        const double* vy, const double* vz);
+void orc2_set_counters(orc2_run* r, int64_t step, double acc_e);
+void orc2_get_grid(const orc2_run* r, double* Q0, double* Q1, double* phi, double* Ex, double* Ey);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,19 @@ def production_sheath(u_over_vti: float = 2.0, ppc: int = 1000, seed: int = 0, *
 PRODUCTION_U_SWEEP = (2.0, 5.0, 10.0, math.inf)
 
 
+def sheath2d(nx: int = 512, ny: int = 512, ppc: int = 64, u_over_vti: float = 3.0, tile: int = 16,
+             sort_every: int = 8, seed: int = 0, **kw) -> dict:
+    """A 2D3V sheath: the 1D geometry in x (symmetry plane at x = 0, wall at
+    x = nx*dx, source in the first cells), periodic in y over ny cells with
+    dy = dx; argon, Te/Ti = 20, u = 3 v_ti, dt = dx/u.  The particles are
+    cell-sorted by blocks of tile x tile cells every ``sort_every`` steps."""
+    cfg = sheath(nx=nx, ppc=ppc, u_over_vti=u_over_vti, te_over_ti=20.0, ion_amu=40.0, seed=seed,
+                 sort_every=sort_every, **kw)
+    cfg["ny"] = int(ny)
+    cfg["tile"] = int(tile)
+    return cfg
+
+
 def batched_sweep(nruns: int = 256, seed: int = 1, ppc_range=(200, 1000), cells_range=(128, 2048),
                   capacity_factor: float = 2.5, **kw) -> list[dict]:
     """Independent 1D sheaths: cells uniform in [128, 2048], ppc uniform in
