@@ -346,6 +346,75 @@ def warm_bench(args) -> int:
     return 0
 
 
+BYTES_PER_PUSH_2D = {"f32": 36, "f64": 72}
+
+
+def cpu_baseline_2d(cfg: dict, budget_s: float = 12.0) -> dict:
+    """The 2D FP64 oracle on a bounded sample: the full 512 x 512 grid with
+    4 particles per cell per species (2,097,152 particles), as many steps as
+    fit the budget (its load and the first deposit and solve untimed)."""
+    import oracle
+    small = dict(cfg)
+    small["species"] = [dict(sp, ppc=4) for sp in cfg["species"]]
+    run = oracle.Run2D(small, cfg["ny"], tile=cfg["tile"])
+    n0 = sum(run.nslots(s) for s in range(2))
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        run.step(1)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n0 * steps / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the 512 x 512 sheath at 4 particles per cell per species ({n0} "
+                      f"particles; the field solve is a plain O(nx ny^2) DFT), FP64 C oracle, one thread"}
+
+
+def run_2d(args, steps: int = 256, warmup: int = 64) -> dict:
+    """The 2D3V sheath (512 x 512 cells, 64 per cell per species, 33,554,432
+    particles, FP32 particles with FP64 grids, tile sort every 8 steps):
+    pushes/s over the timed steps and the push kernel's roofline."""
+    import torch
+    import workloads
+    from paper_1511_08225_amd import slpic
+    cfg = workloads.sheath2d()
+    se = cfg["sort_every"]
+    steps = max(se, steps // se * se)
+    warmup = max(se, warmup // se * se)
+    sim = slpic.Sim2D(cfg, cfg["ny"], precision=args.precision, sort_every=se, tile=cfg["tile"])
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.profile(1)
+    p0 = sim.status()["pushed_total"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.status()
+    pushes = st["pushed_total"] - p0
+    ms, launches = sim.profile_read()["push"]
+    sim.close()
+    bpp = BYTES_PER_PUSH_2D[args.precision]
+    push_ms = ms / max(launches, 1)
+    achieved = bpp * pushes / max(launches, 1) / (push_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle-pushes/s per GPU (2D3V)", "value": pushes / (t1 - t0), "unit": "particle-pushes/s",
+        "steps": steps, "warmup": warmup, "ms_per_step": (t1 - t0) * 1e3 / steps, "dtype": args.precision,
+        "config": {"workload": (f"2D3V argon sheath, {cfg['nx']} x {cfg['ny']} cells (y periodic), 64 particles/"
+                                f"cell/species ({2 * cfg['nx'] * cfg['ny'] * 64} particles at load), Te/Ti=20, "
+                                f"u=3 v_ti, dt={cfg['dt']:.4g}/omega_pe, tile sort ({cfg['tile']}x{cfg['tile']} "
+                                f"cells) every {se} steps")},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push2d",
+                     "bytes_per_push": bpp, "avg_launch_ms": push_ms, "launches": launches},
+        "wall_potential": st["wall_potential"], "error_flags": st["error_flags"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_2d(cfg)
+    return out
+
+
 def launch_params(cfg, args) -> dict:
     """Push chunk, workgroup size, sort period and bucket: from the autotuner
     (cached per workload signature) unless given on the command line."""
@@ -402,6 +471,8 @@ def main() -> int:
     ap.add_argument("--eval-runs", type=int, default=128)
     ap.add_argument("--horizon", type=int, default=8192, help="steps per run in --warm")
     ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--only-2d", action="store_true", help="the 2D3V sheath line alone, and exit")
+    ap.add_argument("--no-2d", action="store_true", help="leave out the 2D3V sheath measurement")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the counter workload (copy calibration + direct-launch steps) and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -422,6 +493,9 @@ def main() -> int:
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
+    if args.only_2d:
+        print(json.dumps(run_2d(args, args.steps, args.warmup)), flush=True)
+        return 0
 
     import workloads
     cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc)
@@ -483,6 +557,8 @@ def main() -> int:
                                "launch": params10, "push_avg_launch_ms": ms10, "achieved_GBs": a10,
                                "frac": a10 / HBM_PEAK_GBS, "bound": "hbm", "peak": HBM_PEAK_GBS,
                                "traffic": traffic_for(10 * args.ppc, params10["chunk"])}
+    if not args.no_2d:
+        line["sheath_2d"] = run_2d(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -1213,9 +1213,11 @@ void orc2_step(orc2_run* r, int32_t nsteps) {
                 double b = beta_of_s2(cfg->beta_kind, cfg->u, norm2(v1));
                 double xn = xt + b * v1[0] * dtdx;
                 double yn = yt + b * v1[1] * dtdx;
-                if (yn < 0.0) yn += (double)ny;
-                else if (yn >= (double)ny) yn -= (double)ny;
-                if (yn >= (double)ny) yn = 0.0; /* -0 rounded onto ny */
+                if (yn < 0.0 || yn >= (double)ny) { /* periodic in y: the remainder */
+                    yn = fmod(yn, (double)ny);
+                    if (yn < 0.0) yn += (double)ny;
+                    if (yn >= (double)ny) yn = 0.0; /* a tiny negative rounded onto ny */
+                }
                 if (xn < 0.0) {
                     xn = -xn;
                     v1[0] = -v1[0];

@@ -27,6 +27,10 @@ UNITS = {
     "kernels_common.hip": ["-ffp-contract=off"],
     "api.cpp": ["-x", "hip"],
     "mlp.hip": [],
+    "kernels2d_f32.hip": [],
+    "kernels2d_f64.hip": ["-ffp-contract=off"],
+    "field2d.hip": ["-ffp-contract=off"],
+    "api2d.cpp": ["-x", "hip"],
 }
 
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "slpic.h"
+#include "host_math.h"
 #include "launch.h"
 #include "slpic_device.h"
 #include "slpic_internal.h"
@@ -22,16 +23,6 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
-
-// <1/beta> over the Maxwell speed density sqrt(2/pi) s^2 exp(-s^2/2), speeds
-// in thermal units, ut = v0/vt.  Eq. (11b): closed form of the split at ut.
-// Eq. (11a): composite five-point Gauss-Legendre quadrature on [0, 40].
-void step_mixture(double ut, double& Ps, double& Pf) {
-    const double c = 0.7978845608028654;  // sqrt(2/pi)
-    double e = std::exp(-0.5 * ut * ut);
-    Ps = std::erf(ut / std::sqrt(2.0)) - c * ut * e;
-    Pf = c * (ut * ut + 2.0) * e / ut;
-}
 
 // ---------------------------------------------------------------------------
 // Warm load planning.  For cell c of species s: n and Gamma linearly
@@ -123,31 +114,6 @@ static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, in
         start += cnt;
     }
     return start;
-}
-
-double mean_inv_beta(int kind, double ut) {
-    if (std::isinf(ut)) return 1.0;
-    if (kind == SLPIC_BETA_STEP) {
-        double Ps, Pf;
-        step_mixture(ut, Ps, Pf);
-        return Ps + Pf;
-    }
-    static const double xg[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831,
-                                 0.9061798459386640};
-    static const double wg[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889,
-                                 0.4786286704993665, 0.2369268850561891};
-    const int panels = 4000;
-    const double L = 40.0, h = L / panels;
-    double sum = 0.0;
-    for (int p = 0; p < panels; ++p) {
-        double mid = (p + 0.5) * h;
-        for (int k = 0; k < 5; ++k) {
-            double s = mid + 0.5 * h * xg[k];
-            double f = 0.7978845608028654 * s * s * std::exp(-0.5 * s * s) * std::sqrt(1.0 + (s / ut) * (s / ut));
-            sum += 0.5 * h * wg[k] * f;
-        }
-    }
-    return sum;
 }
 
 int ceil_log2(int64_t v) {

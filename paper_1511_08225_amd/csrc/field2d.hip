@@ -1,0 +1,213 @@
+// field2d.hip -- the 2D3V field solve (Eq. A2d with eps0 = 1) and the
+// precision-independent step kernels of the 2D library.
+//
+// -lap phi = rho on the (nx+1) x ny nodes, y periodic, dy = dx, node 0 a
+// symmetry plane, phi = 0 at node nx.  A discrete Fourier transform along y
+// (rows are contiguous: one workgroup per x-row, a radix-2 FFT in LDS)
+// turns the five-point stencil into one tridiagonal system along x per mode
+// m with diagonal 2 + 4 sin^2(pi m/ny); those are solved by forward
+// elimination with precomputed pivots and back substitution (one thread per
+// mode, the rows streamed in order), then the inverse transform gives phi and
+// centred differences give E.
+#include <hip/hip_runtime.h>
+
+#include "launch2d.h"
+#include "slpic2d_internal.h"
+
+namespace slpic {
+
+__global__ void k_fill2d(double* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// In-place radix-2 decimation-in-time transform of buf (ny complex values,
+// input in bit-reversed order): X_m = sum_j x_j exp(-+2 pi i m j / ny) with
+// tw[k] = exp(-2 pi i k / ny), k < ny/2, conjugated for the inverse.  The
+// workgroup has ny/2 threads: one butterfly each per stage.
+__device__ void fft_rows(double2* buf, int ny, const double2* __restrict__ tw, bool inverse) {
+    const int t = threadIdx.x;
+    for (int len = 2; len <= ny; len <<= 1) {
+        const int half = len >> 1;
+        const int g = t / half, p = t - g * half;
+        const int i1 = g * len + p, i2 = i1 + half;
+        double2 w = tw[p * (ny / len)];
+        if (inverse) w.y = -w.y;
+        const double2 u = buf[i1], v = buf[i2];
+        const double2 vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+        buf[i1] = make_double2(u.x + vw.x, u.y + vw.y);
+        buf[i2] = make_double2(u.x - vw.x, u.y - vw.y);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int bitrev(int j, int lg) { return (int)(__brev((unsigned)j) >> (32 - lg)); }
+
+// Row i < nx: the right-hand side rho dx^2 = Q dx^2/dV (dV = dx dy, half at
+// node 0, so Q or 2Q) to y-modes.
+__global__ void k_fft_fwd2d(Args2D a, int lg) {
+    const Run2D& R = *a.run;
+    const int ny = R.ny, i = blockIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* buf = (double2*)smem;
+    const double* Q0 = a.Q + (int64_t)i * ny;
+    const double* Q1 = Q0 + R.nodes;
+    const double sc = (i == 0) ? 2.0 : 1.0;
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) buf[bitrev(j, lg)] = make_double2((Q0[j] + Q1[j]) * sc, 0.0);
+    __syncthreads();
+    fft_rows(buf, ny, a.tw, false);
+    double2* out = a.spec + (int64_t)i * ny;
+    for (int m = threadIdx.x; m < ny; m += blockDim.x) out[m] = buf[m];
+}
+
+// Mode m: rows 0..nx-1 of (2 + kappa_m dx^2) phi_i - phi_{i+1} - phi_{i-1} =
+// r_i, with phi_{-1} = phi_1 at the symmetry plane (off-diagonal -2 in row
+// 0) and phi_nx = 0.  Forward: d_i = (r_i + d_{i-1}) / pivot_i.  Back:
+// phi_i = d_i + e_i phi_{i+1} / pivot_i with e_0 = 2, e_i = 1.  In place.
+__global__ void k_thomas2d(Args2D a) {
+    const Run2D& R = *a.run;
+    const int ny = R.ny, nx = R.nx;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= ny) return;
+    double2* sp = a.spec + m;
+    const double* pv = a.tpiv + m;
+    double2 d = make_double2(0.0, 0.0);
+#pragma unroll 8
+    for (int i = 0; i < nx; ++i) {
+        const double2 r = sp[(int64_t)i * ny];
+        const double p = pv[(int64_t)i * ny];
+        d = make_double2((r.x + d.x) * p, (r.y + d.y) * p);
+        sp[(int64_t)i * ny] = d;
+    }
+    double2 ph = d;  // row nx-1
+#pragma unroll 8
+    for (int i = nx - 2; i >= 0; --i) {
+        const double2 di = sp[(int64_t)i * ny];
+        const double e = (i == 0 ? 2.0 : 1.0) * pv[(int64_t)i * ny];
+        ph = make_double2(di.x + e * ph.x, di.y + e * ph.y);
+        sp[(int64_t)i * ny] = ph;
+    }
+}
+
+// Row i < nx: phi from its y-modes; row 0 also gives Phi_w = mean_y phi(0, y)
+// (phi = 0 at the wall).
+__global__ void k_fft_inv2d(Args2D a, int lg) {
+    const Run2D& R = *a.run;
+    const int ny = R.ny, i = blockIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* buf = (double2*)smem;
+    const double2* in = a.spec + (int64_t)i * ny;
+    for (int m = threadIdx.x; m < ny; m += blockDim.x) buf[bitrev(m, lg)] = in[m];
+    __syncthreads();
+    fft_rows(buf, ny, a.tw, true);
+    const double inv = 1.0 / (double)ny;
+    double* phi = a.phi + (int64_t)i * ny;
+    double part = 0.0;
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+        const double v = buf[j].x * inv;
+        phi[j] = v;
+        part += v;
+    }
+    if (i != 0) return;  // workgroup-uniform
+    __syncthreads();
+    double* red = (double*)smem;  // buf is no longer read
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int h = blockDim.x >> 1; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.st->phi_w = red[0] * inv;
+}
+
+// E = -grad phi at every node: centred differences (periodic in y; in x:
+// zero at the symmetry plane, the one-sided second-order difference at the
+// wall), in FP64 and as a float copy for float particles.
+__global__ void k_efield2d(Args2D a) {
+    const Run2D& R = *a.run;
+    const int ny = R.ny, nx = R.nx;
+    const double h = 0.5 / R.dx;
+    const int64_t nodes = R.nodes;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nodes; n += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(n / ny), j = (int)(n - (int64_t)i * ny);
+        const double* p = a.phi;
+        double ex;
+        if (i == 0) ex = 0.0;
+        else if (i < nx) ex = -(p[n + ny] - p[n - ny]) * h;
+        else ex = -(3.0 * p[n] - 4.0 * p[n - ny] + p[n - 2 * ny]) * h;
+        const int jp = (j + 1 == ny) ? 0 : j + 1, jm = (j == 0) ? ny - 1 : j - 1;
+        const int64_t r = (int64_t)i * ny;
+        const double ey = -(p[r + jp] - p[r + jm]) * h;
+        a.E[n] = make_double2(ex, ey);
+        a.E32[n] = make_float2((float)ex, (float)ey);
+    }
+}
+
+// End of a step's particle work: the source plan and push counters applied
+// to the run state, the counters cleared for the next push.
+__global__ void k_finish2d(Args2D a) {
+    State2D* st = a.st;
+    Inject2D* ip = a.inj;
+    if (threadIdx.x == 0) {
+        for (int s = 0; s < 2; ++s) {
+            st->nslots[s] = ip->base[s] + ip->count[s];
+            st->absorbed_total[s] += ip->absorbed[s];
+            st->injected_total[s] += ip->count[s];
+        }
+        st->pushed_total += ip->pushed;
+        st->acc_e = ip->acc_e;
+        st->error |= ip->overflow;
+        ip->overflow = 0;
+        st->step += 1;
+    }
+    for (int j = threadIdx.x; j < 2 * kCountSlots2; j += blockDim.x) a.counts[j] = make_int2(0, 0);
+}
+
+// After the sort scatter: the sorted buffer becomes current and holds exactly
+// the live particles; tile k of species s owns slots [tbeg[k], tbeg[k+1]).
+__global__ void k_sort2d_finish(Args2D a, int nblk) {
+    const Run2D& R = *a.run;
+    State2D* st = a.st;
+    const int nk = R.nkeys;
+    for (int s = 0; s < 2; ++s) {
+        const int* hs = a.hist + R.hoff[s];
+        const int base = hs[0];
+        const int64_t end_entry = R.hoff[s] + (int64_t)nk * R.stiles[s];
+        const long long end = (s == 0) ? (long long)a.hist[end_entry] : a.btot[nblk];
+        const int64_t live = end - base;
+        int64_t* tb = a.tbeg + (int64_t)s * (nk + 1);
+        for (int k = threadIdx.x; k < nk; k += blockDim.x) tb[k] = hs[(int64_t)k * R.stiles[s]] - base;
+        if (threadIdx.x == 0) {
+            tb[nk] = live;
+            st->nslots[s] = live;
+            st->nsorted[s] = live;
+            st->live[s] = live;
+        }
+    }
+    if (threadIdx.x == 0) *a.cur ^= 1;
+}
+
+void launch2d_fill(double* p, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill2d, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, n);
+}
+
+void launch2d_field(const Args2D& a, int nx, int ny, hipStream_t s) {
+    int lg = 0;
+    while ((1 << lg) < ny) ++lg;
+    const size_t lds = sizeof(double2) * (size_t)ny;
+    hipLaunchKernelGGL(k_fft_fwd2d, dim3(nx), dim3(ny / 2), lds, s, a, lg);
+    hipLaunchKernelGGL(k_thomas2d, dim3((ny + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_fft_inv2d, dim3(nx), dim3(ny / 2), lds, s, a, lg);
+    const int64_t nodes = (int64_t)(nx + 1) * ny;
+    hipLaunchKernelGGL(k_efield2d, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 8192)), dim3(256), 0, s, a);
+}
+
+void launch2d_finish(const Args2D& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish2d, dim3(1), dim3(128), 0, s, a);
+}
+
+void launch2d_sort_finish(const Args2D& a, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_sort2d_finish, dim3(1), dim3(256), 0, s, a, nblk);
+}
+
+}  // namespace slpic

@@ -192,11 +192,14 @@ void launch_field_step(const KArgs& a, int nruns, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL(k_field_step, dim3(nruns), dim3(kFieldThreads), lds, s, a);
 }
 int scan_blocks(int64_t n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
-void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s) {
-    const int nblk = scan_blocks(hist_entries);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(1024), 0, s, a.hist, hist_entries, btot);
+void launch_scan_ints(int* h, int64_t n, long long* btot, hipStream_t s) {
+    const int nblk = scan_blocks(n);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(1024), 0, s, h, n, btot);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, btot, nblk);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(1024), 0, s, a.hist, hist_entries, (const long long*)btot);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(1024), 0, s, h, n, (const long long*)btot);
+}
+void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s) {
+    launch_scan_ints(a.hist, hist_entries, btot, s);
 }
 void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const long long* btot,
                         hipStream_t s) {

@@ -31,6 +31,8 @@ void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_
 void launch_field_step(const KArgs& a, int nruns, size_t lds, hipStream_t s);
 int scan_blocks(int64_t hist_entries);
 void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s);
+// exclusive scan of n ints in place; btot[scan_blocks(n)] receives the total
+void launch_scan_ints(int* h, int64_t n, long long* btot, hipStream_t s);
 void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const long long* btot,
                         hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);

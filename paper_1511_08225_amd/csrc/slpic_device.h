@@ -46,9 +46,11 @@ struct Stream {
     U4 buf;
     int pos;
     __device__ Stream(const RunInfo& R, uint32_t index, uint32_t step, int purpose, int species)
-        : c0(index), c1(step), c2(R.run_id),
-          c3(((uint32_t)purpose << 24) | ((uint32_t)species << 20)), k0(R.seed_lo), k1(R.seed_hi),
-          pos(4) {}
+        : Stream(R.run_id, R.seed_lo, R.seed_hi, index, step, purpose, species) {}
+    __device__ Stream(uint32_t run_id, uint32_t seed_lo, uint32_t seed_hi, uint32_t index, uint32_t step,
+                      int purpose, int species)
+        : c0(index), c1(step), c2(run_id), c3(((uint32_t)purpose << 24) | ((uint32_t)species << 20)),
+          k0(seed_lo), k1(seed_hi), pos(4) {}
     __device__ double next() {
         if (pos >= 4) {
             buf = philox10(c0, c1, c2, c3, k0, k1);
@@ -134,6 +136,50 @@ __device__ __forceinline__ double beta_deposit(T vx, T c2, double u, double u2, 
     double y = __builtin_amdgcn_rsq(s2);
     y = y * (1.5 - 0.5 * s2 * y * y);
     return u * y;
+}
+
+// ---------------------------------------------------------------------------
+// Cold load: g0 = f0/beta (Eq. 5).  Speeds from the g-speed density of
+// Eq. (11b) (a mixture of the Maxwell speed density below v0 and
+// s^3 e^{-s^2/2} above it), or of Eq. (11a) by rejection from it; isotropic
+// directions; uniform positions.  The uniform draws of one particle come in
+// a fixed order from its own counter-based stream, so runs are reproducible.
+// ---------------------------------------------------------------------------
+__device__ inline double sample_g_speed_step(Stream& st, double ut, double Ps, double Pf) {
+    double usel = st.next();
+    if (usel * (Ps + Pf) < Ps) {
+        for (int attempt = 0; attempt < 100000; ++attempt) {
+            if (ut <= 1.0) {
+                double s = ut * cbrt(st.next());
+                double acc = st.next();
+                if (acc < exp(-0.5 * s * s)) return s;
+            } else {
+                double z[3];
+                st.normal3(z);
+                double s = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+                if (s <= ut) return s;
+            }
+        }
+        return 0.0;
+    }
+    double t0 = 0.5 * ut * ut;
+    double uc = st.next();
+    double y = -log(1.0 - st.next());
+    if (!(uc * (t0 + 1.0) < t0)) {
+        double y2 = -log(1.0 - st.next());
+        y += y2;
+    }
+    return sqrt(2.0 * (t0 + y));
+}
+
+__device__ inline double sample_g_speed(Stream& st, int bk, double ut, double Ps, double Pf) {
+    if (bk == kBetaStep) return sample_g_speed_step(st, ut, Ps, Pf);
+    for (int attempt = 0; attempt < 100000; ++attempt) {
+        double s = sample_g_speed_step(st, ut, Ps, Pf);
+        double r = sqrt(1.0 + (s / ut) * (s / ut)) / (sqrt(2.0) * fmax(1.0, s / ut));
+        if (st.next() < r) return s;
+    }
+    return 0.0;
 }
 
 template <typename T> struct Eps;
@@ -304,6 +350,7 @@ struct CellMap {
     int fb;
     float inv_fscale;
     __device__ explicit CellMap(const RunInfo& R) : fb(R.fb), inv_fscale((float)R.inv_fscale) {}
+    __device__ CellMap(int fb_, float inv_fscale_) : fb(fb_), inv_fscale(inv_fscale_) {}
 };
 template <typename T> struct PosT;
 template <> struct PosT<float> {

@@ -68,6 +68,27 @@ class RunStatus(ctypes.Structure):
                 "window_mean": list(self.window_mean), "moment_samples": self.moment_samples}
 
 
+class Tuning2D(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("margin", ctypes.c_int32), ("per_thread", ctypes.c_int32), ("tail_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class Status2D(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("nslots", ctypes.c_int64 * 2), ("nsorted", ctypes.c_int64 * 2),
+                ("capacity", ctypes.c_int64 * 2), ("absorbed_total", ctypes.c_int64 * 2),
+                ("injected_total", ctypes.c_int64 * 2), ("pushed_total", ctypes.c_int64),
+                ("acc_e", ctypes.c_double), ("wall_potential", ctypes.c_double),
+                ("error_flags", ctypes.c_int32), ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2)]
+
+    def as_dict(self) -> dict:
+        return {"step": self.step, "nslots": list(self.nslots), "nsorted": list(self.nsorted),
+                "capacity": list(self.capacity), "absorbed_total": list(self.absorbed_total),
+                "injected_total": list(self.injected_total), "pushed_total": self.pushed_total,
+                "acc_e": self.acc_e, "wall_potential": self.wall_potential, "error_flags": self.error_flags,
+                "fixed_bits": self.fixed_bits, "weight": list(self.weight)}
+
+
 _lib = None
 _P = ctypes.c_void_p
 _PD = ctypes.POINTER(ctypes.c_double)
@@ -112,6 +133,23 @@ def lib():
             "slpic_profile_read": (ctypes.c_int, [_P, _PD, _PI64]),
             "slpic_total_slots": (ctypes.c_int, [_P, _PI64]),
             "slpic_destroy": (None, [_P]),
+            "slpic2d_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(RunConfig), i32,
+                                                          ctypes.POINTER(Tuning2D)]),
+            "slpic2d_init": (ctypes.c_int, [ctypes.POINTER(RunConfig), i32, ctypes.POINTER(Tuning2D), _P,
+                                            ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+            "slpic2d_step": (ctypes.c_int, [_P, i32, _P]),
+            "slpic2d_refresh_fields": (ctypes.c_int, [_P, _P]),
+            "slpic2d_solve_charge": (ctypes.c_int, [_P, _P, _P]),
+            "slpic2d_export_grid": (ctypes.c_int, [_P, _PD, _PD, _PD]),
+            "slpic2d_export_particles": (ctypes.c_int, [_P, i32, _PD, _PD, _PD, _PD, _PD, _PI64]),
+            "slpic2d_import_particles": (ctypes.c_int, [_P, i32, _PD, _PD, _PD, _PD, _PD, i64]),
+            "slpic2d_set_counters": (ctypes.c_int, [_P, i64, ctypes.c_double]),
+            "slpic2d_sort_now": (ctypes.c_int, [_P, _P]),
+            "slpic2d_export_perm": (ctypes.c_int, [_P, i32, _PI32, _PI64]),
+            "slpic2d_status_query": (ctypes.c_int, [_P, ctypes.POINTER(Status2D)]),
+            "slpic2d_profile": (ctypes.c_int, [_P, i32]),
+            "slpic2d_profile_read": (ctypes.c_int, [_P, _PD, _PI64]),
+            "slpic2d_destroy": (None, [_P]),
             "slpic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
@@ -401,3 +439,107 @@ class Mlp:
                                     _P(self.v.data_ptr()), _P(self.grads.data_ptr()), float(lr), float(beta1),
                                     float(beta2), float(eps), self.step, self._stream()), "slpic_mlp_adam")
 
+
+
+class Sim2D:
+    """One 2D3V sheath (y periodic over ny cells, dy = dx) on one GPU."""
+
+    def __init__(self, config: dict, ny: int, precision="f32", sort_every=8, tile=16, margin=0, per_thread=0,
+                 tail_groups=0, device="cuda"):
+        self.config = dict(config)
+        self.nx, self.ny = int(config["nx"]), int(ny)
+        self.precision = precision
+        self._cfg = run_config(self.config)
+        t = Tuning2D()
+        t.precision = {"f32": SLPIC_F32, "f64": SLPIC_F64}[precision]
+        t.sort_every, t.tile, t.margin = int(sort_every), int(tile), int(margin)
+        t.per_thread, t.tail_groups = int(per_thread), int(tail_groups)
+        self._tun = t
+        L = lib()
+        nbytes = L.slpic2d_workspace_bytes(ctypes.byref(self._cfg), self.ny, ctypes.byref(t))
+        if nbytes == 0:
+            raise SlpicError("invalid 2D configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.workspace_bytes = nbytes
+        self._ctx = _P()
+        _check(L.slpic2d_init(ctypes.byref(self._cfg), self.ny, ctypes.byref(t), _P(self._ws_ptr), nbytes,
+                              self._stream(), ctypes.byref(self._ctx)), "slpic2d_init")
+
+    def _stream(self):
+        return _P(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            torch.cuda.synchronize(self.device)
+            lib().slpic2d_destroy(self._ctx)
+            self._ctx = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        _check(lib().slpic2d_step(self._ctx, int(n), self._stream()), "slpic2d_step")
+
+    def refresh_fields(self):
+        _check(lib().slpic2d_refresh_fields(self._ctx, self._stream()), "slpic2d_refresh_fields")
+
+    def solve_charge(self, Q):
+        """phi and E from a node charge array (2, nx+1, ny) (rho = Q/dV)."""
+        q = torch.as_tensor(np.ascontiguousarray(Q, dtype=np.float64)).to(self.device)
+        _check(lib().slpic2d_solve_charge(self._ctx, _P(q.data_ptr()), self._stream()), "slpic2d_solve_charge")
+        torch.cuda.synchronize(self.device)
+
+    def sort_now(self):
+        _check(lib().slpic2d_sort_now(self._ctx, self._stream()), "slpic2d_sort_now")
+
+    def status(self) -> dict:
+        st = Status2D()
+        _check(lib().slpic2d_status_query(self._ctx, ctypes.byref(st)), "slpic2d_status_query")
+        return st.as_dict()
+
+    def grid(self):
+        shape = (self.nx + 1, self.ny)
+        nodes = shape[0] * shape[1]
+        Q, phi, E = np.zeros(2 * nodes), np.zeros(nodes), np.zeros(2 * nodes)
+        _check(lib().slpic2d_export_grid(self._ctx, _dp(Q), _dp(phi), _dp(E)), "slpic2d_export_grid")
+        E = E.reshape(2, *shape)
+        return {"Q": Q.reshape(2, *shape), "phi": phi.reshape(shape), "Ex": E[0], "Ey": E[1]}
+
+    def export_particles(self, species: int):
+        """(x, y, vx, vy, vz^2) of the occupied slots (dead slots x < 0)."""
+        cnt = self.status()["nslots"][species]
+        arrs = [np.zeros(max(cnt, 1)) for _ in range(5)]
+        n = ctypes.c_int64(len(arrs[0]))
+        _check(lib().slpic2d_export_particles(self._ctx, species, *[_dp(a) for a in arrs], ctypes.byref(n)),
+               "slpic2d_export_particles")
+        return tuple(a[: n.value] for a in arrs)
+
+    def import_particles(self, species: int, x, y, vx, vy, vz2):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, vx, vy, vz2)]
+        _check(lib().slpic2d_import_particles(self._ctx, species, *[_dp(a) for a in arrs], len(arrs[0])),
+               "slpic2d_import_particles")
+
+    def set_counters(self, step: int, acc_e: float):
+        _check(lib().slpic2d_set_counters(self._ctx, int(step), float(acc_e)), "slpic2d_set_counters")
+
+    def perm(self, species: int) -> np.ndarray:
+        cnt = max(self.status()["capacity"][species], 1)
+        p = np.zeros(cnt, dtype=np.int32)
+        n = ctypes.c_int64(cnt)
+        _check(lib().slpic2d_export_perm(self._ctx, species, p.ctypes.data_as(_PI32), ctypes.byref(n)),
+               "slpic2d_export_perm")
+        return p[: n.value]
+
+    def profile(self, enable: int):
+        _check(lib().slpic2d_profile(self._ctx, int(enable)), "slpic2d_profile")
+
+    def profile_read(self):
+        ms = np.zeros(4)
+        cnt = np.zeros(4, dtype=np.int64)
+        _check(lib().slpic2d_profile_read(self._ctx, _dp(ms), cnt.ctypes.data_as(_PI64)), "slpic2d_profile_read")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_CLASSES)}

@@ -17,7 +17,7 @@ def _declared_functions():
         if fn.endswith(".h"):
             text = open(os.path.join(ROOT, "include", fn)).read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names |= set(re.findall(r"\b(slpic_\w+)\s*\(", text))
+            names |= set(re.findall(r"\b(slpic(?:2d)?_\w+)\s*\(", text))
     return sorted(names)
 
 
@@ -82,3 +82,32 @@ def test_init_rejects_bad_workspace_without_touching_gpu():
     rc = L.slpic_init(ctypes.byref(c), 1, ctypes.byref(t), ctypes.c_void_p(1 << 20), 16, None,
                       ctypes.byref(ctx))
     assert rc == -2 and not ctx.value
+
+
+def test_2d_workspace_planning_validates_configs():
+    import torch  # noqa: F401
+    import workloads
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    cfg = workloads.sheath2d(nx=64, ny=64, ppc=4)
+    good = slpic.run_config(cfg)
+    t = slpic.Tuning2D()
+    n = L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(t))
+    assert n > 0
+    assert "slpic2d_step" in _declared_functions()
+    # ny must be a power of two in [4, 2048]
+    for ny in (3, 48, 4096):
+        assert L.slpic2d_workspace_bytes(ctypes.byref(good), ny, ctypes.byref(t)) == 0, ny
+    # too many sort blocks for the LDS histogram, bad tile/per_thread values
+    for field, val in (("tile", 100), ("per_thread", 3), ("margin", 40), ("precision", 5)):
+        tb = slpic.Tuning2D()
+        setattr(tb, field, val)
+        assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(tb)) == 0, field
+    big = slpic.run_config(workloads.sheath2d(nx=2048, ny=2048, ppc=1))
+    tb = slpic.Tuning2D()
+    tb.tile = 16  # 128 x 128 = 16384 blocks > 4096
+    assert L.slpic2d_workspace_bytes(ctypes.byref(big), 2048, ctypes.byref(tb)) == 0
+    # F64 needs more bytes than F32
+    t64 = slpic.Tuning2D()
+    t64.precision = slpic.SLPIC_F64
+    assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(t64)) > n
