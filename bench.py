@@ -65,6 +65,15 @@ def traffic_probe(args) -> int:
     torch.cuda.synchronize()
     del src, dst
     torch.cuda.empty_cache()
+    if args.only_2d:
+        cfg = workloads.sheath2d()
+        sim = slpic.Sim2D(cfg, cfg["ny"], precision=args.precision, sort_every=cfg["sort_every"], tile=cfg["tile"])
+        sim.step(args.steps)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "workload": "sheath2d", "steps": args.steps,
+                          "pushed": sim.status()["pushed_total"]}), flush=True)
+        sim.close()
+        return 0
     cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc)
     params = launch_params(cfg, args)
     sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
@@ -77,16 +86,17 @@ def traffic_probe(args) -> int:
     return 0
 
 
-def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int) -> int:
+def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int, two_d: bool = False) -> int:
     """Per-launch HBM bytes of the push from two rocprofv3 --pmc counter files
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
     counter reads for the 1 GiB copy; written where the benchmark reads it."""
     import csv
+    kernel = "k_push2d" if two_d else "k_push_deposit"
 
     def per_kernel(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        push = [float(r["Counter_Value"]) for r in rows if "k_push_deposit" in r["Kernel_Name"]
+        push = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]
                 and ", true," in r["Kernel_Name"]]
         return copy, push
 
@@ -100,16 +110,25 @@ def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int) -> int:
     w_scale = gib_kib / max(wc)
     fetch = sum(fp) / len(fp) * f_scale * 1024.0
     write = sum(wp) / len(wp) * w_scale * 1024.0
-    out = {"workload": "production_sheath", "ppc": ppc, "chunk": chunk, "launches": len(fp),
+    out = {"workload": "sheath2d" if two_d else "production_sheath", "ppc": ppc, "chunk": chunk,
+           "launches": len(fp),
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale,
            "copy_fetch_kib": max(fc), "copy_write_kib": max(wc)}
     table = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
-    table[str(ppc)] = out
+    table["sheath2d" if two_d else str(ppc)] = out
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(table, f, indent=1)
     print(json.dumps(out))
     return 0
+
+
+def traffic_for_2d(tile: int):
+    """Counter-measured HBM bytes per 2D push launch, if recorded for this tile."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE)).get("sheath2d")
+    return t.get("bytes_per_launch") if t and t.get("chunk") == tile else None
 
 
 def traffic_for(ppc: int, chunk: int):
@@ -406,7 +425,7 @@ def run_2d(args, steps: int = 256, warmup: int = 64) -> dict:
                                 f"u=3 v_ti, dt={cfg['dt']:.4g}/omega_pe, tile sort ({cfg['tile']}x{cfg['tile']} "
                                 f"cells) every {se} steps")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push2d",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for_2d(cfg["tile"]), "kernel": "k_push2d",
                      "bytes_per_push": bpp, "avg_launch_ms": push_ms, "launches": launches},
         "wall_potential": st["wall_potential"], "error_flags": st["error_flags"],
     }
@@ -480,6 +499,10 @@ def main() -> int:
     args = ap.parse_args()
     if args.traffic_from:
         import workloads
+        if args.only_2d:  # the record keeps the sort tile in its "chunk" field
+            c2 = workloads.sheath2d()
+            return traffic_from(args.traffic_from[0], args.traffic_from[1], c2["species"][0]["ppc"], c2["tile"],
+                                two_d=True)
         chunk = launch_params(workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc), args)["chunk"]
         return traffic_from(args.traffic_from[0], args.traffic_from[1], args.ppc, chunk)
     if args.traffic_probe:

@@ -44,15 +44,17 @@ typedef struct {
     int32_t precision;   /* SLPIC_F32 (int32 fixed-point coordinates, float      */
                          /* velocities) or SLPIC_F64; grids are FP64 in both     */
     int32_t sort_every;  /* tile sort + compaction every k steps; 0 = never      */
-    int32_t tile;        /* sort blocks of tile x tile cells, 1..64; 0 = 16;      */
+    int32_t tile;        /* sort blocks of tile x tile cells, 1..64; 0 = 8;       */
                          /* ceil(nx/tile) * ceil(ny/tile) must not exceed 4096   */
     int32_t margin;      /* cells of the LDS node window beyond a block; 0 =     */
                          /* max(1, sort_every) (with dt <= dx/u no particle      */
                          /* leaves it between two sorts; those that do use the   */
                          /* grid directly)                                       */
-    int32_t per_thread;  /* particles per push thread and pass: 1, 2, 4, 8; 0 = 4 */
+    int32_t per_thread;  /* particles per push thread and pass: 1, 2, 4, 8; 0 = 1 */
     int32_t tail_groups; /* workgroups over the unsorted tail; 0 = 512           */
-    int32_t reserved[2];
+    int32_t sort_tile;   /* slots per sort workgroup, a multiple of 1024 up to   */
+                         /* 2^20; 0 = 65536                                      */
+    int32_t reserved;
 } slpic2d_tuning;
 
 typedef struct {

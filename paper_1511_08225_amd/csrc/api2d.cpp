@@ -22,7 +22,6 @@ namespace {
 
 constexpr size_t kAlign2 = 256;
 size_t up2(size_t n) { return (n + kAlign2 - 1) / kAlign2 * kAlign2; }
-constexpr int kSortTile2 = 16384;  // slots per sort workgroup
 constexpr int kInjectGroups2 = 16;
 
 #define HIP2_TRY(x)                                    \
@@ -54,16 +53,18 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     slpic2d_tuning t{};
     if (tin) t = *tin;
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
-    if (t.sort_every < 0 || t.tile < 0 || t.margin < 0 || t.per_thread < 0 || t.tail_groups < 0)
+    if (t.sort_every < 0 || t.tile < 0 || t.margin < 0 || t.per_thread < 0 || t.tail_groups < 0 || t.sort_tile < 0)
         return SLPIC_EINVAL;
-    if (t.tile == 0) t.tile = 16;
+    if (t.tile == 0) t.tile = 8;
     if (t.margin == 0) t.margin = std::max(1, t.sort_every);
-    if (t.per_thread == 0) t.per_thread = 4;
+    if (t.per_thread == 0) t.per_thread = 1;
     if (t.tail_groups == 0) t.tail_groups = 512;
+    if (t.sort_tile == 0) t.sort_tile = 65536;
+    if (t.sort_tile < 1024 || t.sort_tile > (1 << 20) || (t.sort_tile & 1023)) return SLPIC_EINVAL;
     if (t.tile > 64 || t.margin > 32 || t.tail_groups > 65536) return SLPIC_EINVAL;
     if (t.per_thread != 1 && t.per_thread != 2 && t.per_thread != 4 && t.per_thread != 8) return SLPIC_EINVAL;
     if (ny < 4 || ny > 2048 || (ny & (ny - 1))) return SLPIC_EINVAL;
-    if (c->nx < 4 || c->nx > (1 << 16) || !(c->dx > 0) || !(c->dt > 0) || !(c->u > 0) || c->nspecies != 2 ||
+    if (c->nx < 4 || c->nx > 1024 || !(c->dx > 0) || !(c->dt > 0) || !(c->u > 0) || c->nspecies != 2 ||
         c->source_cells < 1 || c->source_cells > c->nx || c->warm_profile ||
         (c->beta_kind != SLPIC_BETA_STEP && c->beta_kind != SLPIC_BETA_SMOOTH))
         return SLPIC_EINVAL;
@@ -82,7 +83,8 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     if (R.nkeys > 4096) return SLPIC_EINVAL;
     R.margin = t.margin;
     R.win = t.tile + 2 * t.margin + 1;
-    R.sort_tile = kSortTile2;
+    R.sort_tile = t.sort_tile;
+    R.tile_shift = (t.tile & (t.tile - 1)) ? -1 : clog2(t.tile);
     R.dx = c->dx;
     R.dt = c->dt;
     R.u = c->u;
@@ -116,7 +118,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
         if (R.cap[s] > (int64_t(1) << 31) - 1) return SLPIC_EINVAL;
         R.poff[s] = poff;
         poff += R.cap[s];
-        R.stiles[s] = (int32_t)((R.cap[s] + kSortTile2 - 1) / kSortTile2);
+        R.stiles[s] = (int32_t)((R.cap[s] + t.sort_tile - 1) / t.sort_tile);
         R.hoff[s] = hoff;
         hoff += (int64_t)R.nkeys * R.stiles[s];
     }
@@ -153,7 +155,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     L.E = take(sizeof(double2) * R.nodes);
     L.E32 = take(sizeof(float2) * R.nodes);
     L.spec = take(sizeof(double2) * (size_t)R.nx * ny);
-    L.tpiv = take(sizeof(double) * (size_t)R.nx * ny);
+    L.tpiv = take(sizeof(double) * (size_t)(ny / 2 + 1) * R.nx);
     L.tw = take(sizeof(double2) * (size_t)(ny / 2));
     L.hist = take(sizeof(int) * P.hist_entries);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
@@ -320,22 +322,23 @@ int slpic2d_init(const slpic_run_config* run, int32_t ny, const slpic2d_tuning* 
     a.hist = (int*)(w + L.hist);
     a.btot = (long long*)(w + L.btot);
     a.tbeg = (int64_t*)(w + L.tbeg);
-    // field-solve tables: twiddles exp(-2 pi i k/ny) and, per mode, the
-    // pivots of the elimination of diag 2 + 4 sin^2(pi m/ny), off-diagonals
-    // -1 (row 0: -2 towards row 1)
+    // field-solve tables: twiddles exp(-2 pi i k/ny) and, per y-mode m <=
+    // ny/2, the pivots of the elimination of its x-system (diagonal 2 +
+    // 4 sin^2(pi m/ny) with dy = dx, off-diagonals -1, row 0 coupled to row 1
+    // by -2): p_i = 1 / (diag + c'_{i-1}), c'_0 = -2 p_0, c'_i = -p_i
     std::vector<double2> tw(ny / 2);
     for (int k = 0; k < ny / 2; ++k) {
         const double ang = 2.0 * M_PI * (double)k / (double)ny;
         tw[k] = make_double2(std::cos(ang), -std::sin(ang));
     }
-    std::vector<double> piv((size_t)R.nx * ny);
-    for (int m = 0; m < ny; ++m) {
+    std::vector<double> piv((size_t)(ny / 2 + 1) * R.nx);
+    for (int m = 0; m <= ny / 2; ++m) {
         const double sm = std::sin(M_PI * (double)m / (double)ny);
-        const double b = 2.0 + 4.0 * sm * sm;
+        const double diag = 2.0 + 4.0 * sm * sm;
         double cp = 0.0;
         for (int i = 0; i < R.nx; ++i) {
-            const double p = 1.0 / (b + cp);  // b - a_i c'_{i-1}, a_i = -1 (a_0 = 0, c'_{-1} = 0)
-            piv[(size_t)i * ny + m] = p;
+            const double p = 1.0 / (diag + cp);
+            piv[(size_t)m * R.nx + i] = p;
             cp = (i == 0 ? -2.0 : -1.0) * p;
         }
     }

@@ -5,10 +5,10 @@
 // symmetry plane, phi = 0 at node nx.  A discrete Fourier transform along y
 // (rows are contiguous: one workgroup per x-row, a radix-2 FFT in LDS)
 // turns the five-point stencil into one tridiagonal system along x per mode
-// m with diagonal 2 + 4 sin^2(pi m/ny); those are solved by forward
-// elimination with precomputed pivots and back substitution (one thread per
-// mode, the rows streamed in order), then the inverse transform gives phi and
-// centred differences give E.
+// m with diagonal 2 + 4 sin^2(pi m/ny); those are solved by elimination with
+// precomputed pivots, its two recurrences evaluated as scans in LDS (one
+// workgroup per mode), then the inverse transform gives phi and centred
+// differences give E.
 #include <hip/hip_runtime.h>
 
 #include "launch2d.h"
@@ -61,32 +61,62 @@ __global__ void k_fft_fwd2d(Args2D a, int lg) {
 }
 
 // Mode m: rows 0..nx-1 of (2 + kappa_m dx^2) phi_i - phi_{i+1} - phi_{i-1} =
-// r_i, with phi_{-1} = phi_1 at the symmetry plane (off-diagonal -2 in row
-// 0) and phi_nx = 0.  Forward: d_i = (r_i + d_{i-1}) / pivot_i.  Back:
-// phi_i = d_i + e_i phi_{i+1} / pivot_i with e_0 = 2, e_i = 1.  In place.
-__global__ void k_thomas2d(Args2D a) {
+// r_i, with phi_{-1} = phi_1 at the symmetry plane (coefficient -2 towards
+// row 1 in row 0) and phi_nx = 0.  Gaussian elimination without pivoting
+// (the Thomas algorithm) with the pivots p_i precomputed per mode: forward
+// d_i = p_i (r_i + d_{i-1}), back phi_i = d_i + e_i p_i phi_{i+1} (e_0 = 2,
+// e_i = 1).  Both are first-order linear recurrences, i.e. compositions of
+// affine maps, evaluated as inclusive scans in LDS (one thread per row,
+// ceil(log2 nx) doubling steps each way): the same terms as the sequential
+// recurrence, summed as a tree.  Real input makes mode ny - m the complex
+// conjugate of mode m (same coefficients): modes 0..ny/2 are solved and the
+// others written as conjugates.
+__global__ void k_tri2d(Args2D a) {
     const Run2D& R = *a.run;
-    const int ny = R.ny, nx = R.nx;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= ny) return;
-    double2* sp = a.spec + m;
-    const double* pv = a.tpiv + m;
-    double2 d = make_double2(0.0, 0.0);
-#pragma unroll 8
-    for (int i = 0; i < nx; ++i) {
-        const double2 r = sp[(int64_t)i * ny];
-        const double p = pv[(int64_t)i * ny];
-        d = make_double2((r.x + d.x) * p, (r.y + d.y) * p);
-        sp[(int64_t)i * ny] = d;
+    const int ny = R.ny, n = R.nx, m = blockIdx.x;
+    const int i = threadIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2* Bs = (double2*)smem;
+    double* As = (double*)(Bs + n);
+    const bool row = i < n;
+    const double p = row ? a.tpiv[(int64_t)m * n + i] : 0.0;
+    const double2 r = row ? a.spec[(int64_t)i * ny + m] : make_double2(0.0, 0.0);
+    // forward: F_i = f_i o f_{i-1} o ... o f_0 with f_i(x) = p_i x + p_i r_i
+    double A = p;
+    double2 B = make_double2(p * r.x, p * r.y);
+    for (int s = 1; s < n; s <<= 1) {
+        if (row) {
+            As[i] = A;
+            Bs[i] = B;
+        }
+        __syncthreads();
+        if (row && i >= s) {
+            const double A1 = As[i - s];
+            const double2 B1 = Bs[i - s];
+            B = make_double2(A * B1.x + B.x, A * B1.y + B.y);
+            A = A * A1;
+        }
+        __syncthreads();
     }
-    double2 ph = d;  // row nx-1
-#pragma unroll 8
-    for (int i = nx - 2; i >= 0; --i) {
-        const double2 di = sp[(int64_t)i * ny];
-        const double e = (i == 0 ? 2.0 : 1.0) * pv[(int64_t)i * ny];
-        ph = make_double2(di.x + e * ph.x, di.y + e * ph.y);
-        sp[(int64_t)i * ny] = ph;
+    // back: G_i = g_i o g_{i+1} o ... o g_{n-1} with g_i(y) = e_i p_i y + d_i, at y = 0
+    A = (i == 0 ? 2.0 : 1.0) * p;
+    for (int s = 1; s < n; s <<= 1) {
+        if (row) {
+            As[i] = A;
+            Bs[i] = B;
+        }
+        __syncthreads();
+        if (row && i + s < n) {
+            const double A2 = As[i + s];
+            const double2 B2 = Bs[i + s];
+            B = make_double2(A * B2.x + B.x, A * B2.y + B.y);
+            A = A * A2;
+        }
+        __syncthreads();
     }
+    if (!row) return;
+    a.spec[(int64_t)i * ny + m] = B;
+    if (m > 0 && m < ny / 2) a.spec[(int64_t)i * ny + (ny - m)] = make_double2(B.x, -B.y);
 }
 
 // Row i < nx: phi from its y-modes; row 0 also gives Phi_w = mean_y phi(0, y)
@@ -196,7 +226,8 @@ void launch2d_field(const Args2D& a, int nx, int ny, hipStream_t s) {
     while ((1 << lg) < ny) ++lg;
     const size_t lds = sizeof(double2) * (size_t)ny;
     hipLaunchKernelGGL(k_fft_fwd2d, dim3(nx), dim3(ny / 2), lds, s, a, lg);
-    hipLaunchKernelGGL(k_thomas2d, dim3((ny + 63) / 64), dim3(64), 0, s, a);
+    const int rows = (nx + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_tri2d, dim3(ny / 2 + 1), dim3(rows), (size_t)nx * 24, s, a);
     hipLaunchKernelGGL(k_fft_inv2d, dim3(nx), dim3(ny / 2), lds, s, a, lg);
     const int64_t nodes = (int64_t)(nx + 1) * ny;
     hipLaunchKernelGGL(k_efield2d, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 8192)), dim3(256), 0, s, a);

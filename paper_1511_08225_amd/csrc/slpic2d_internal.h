@@ -21,7 +21,7 @@ struct Run2D {
     int32_t win;           // window side in nodes: tile + 2 margin + 1
     int32_t stiles[2];     // sort slot tiles per species
     int32_t sort_tile;     // slots per sort slot tile
-    int32_t pad;
+    int32_t tile_shift;    // log2(tile) when tile is a power of two, else -1
     double dx, dt, u, u2, dtdx;
     double fscale, inv_fscale;
     double qm[2], qw[2], w[2], vt[2], mass[2], Ps[2], Pf[2], ut[2];
@@ -69,7 +69,7 @@ struct Args2D {
     double2* E;      // (Ex, Ey) [nodes]
     float2* E32;     // float copy of E
     double2* spec;   // y-Fourier modes of the field solve [nx][ny]
-    const double* tpiv;  // Thomas elimination: 1 / pivot per (row, mode) [nx][ny]
+    const double* tpiv;  // elimination pivots of the x-system per y-mode [ny/2 + 1][nx]
     const double2* tw;   // exp(-2 pi i k / ny), k < ny/2
     int* hist;       // sort histograms [species][key][slot tile]
     long long* btot; // scan block totals

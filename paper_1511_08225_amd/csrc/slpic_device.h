@@ -120,11 +120,9 @@ __device__ __forceinline__ T beta_s2(T s2, T u, T u2, bool uinf) {
 }
 
 // beta of Eq. (11a)/(11b) in FP64 from the stored particle velocity, for the
-// charge deposit.  Float particles: the quasi-neutral net charge is ~1e-3 of
-// either species' charge, so float rounding of the deposit weight would be
-// amplified ~1e3 in E; the weight is taken in double instead (hardware
-// reciprocal square root plus one Newton step, ~1e-13).  Double particles
-// use the correctly rounded form.
+// charge of injected particles and the moments (float particles: hardware
+// reciprocal square root plus one Newton step, ~1e-13; double particles: the
+// correctly rounded form).
 template <int BK, typename T>
 __device__ __forceinline__ double beta_deposit(T vx, T c2, double u, double u2, bool uinf) {
     if (uinf) return 1.0;
@@ -219,11 +217,23 @@ __device__ __forceinline__ T series_inverse(T al, T kap) {
     return kap * (T(1) + kap * (c2 + kap * (c3 + kap * (c4 + kap * (c5 + kap * (c6 + kap * (c7 + kap * c8)))))));
 }
 
+// The same series through kappa^4: for kappa <= 0.01 the first omitted term
+// c_5 kappa^5 (|c_5| <= 4 for |alpha| <= 1) is below 4e-10 s0.
+template <typename T>
+__device__ __forceinline__ T series_inverse4(T al, T kap) {
+    const T a2 = al * al;
+    const T c2 = T(-0.5) * al;
+    const T c3 = (T(4) * a2 - T(1)) * T(1.0 / 6.0);
+    const T c4 = al * (T(13) - T(28) * a2) * T(1.0 / 24.0);
+    return kap * (T(1) + kap * (c2 + kap * (c3 + kap * c4)));
+}
+
 // p1 >= p0 with G_c(p1) - G_c(p0) = K.
 //  - c = 0: closed form, p1|p1| = p0|p0| + 2K.
 //  - kappa = K/s0^2 < 1/4: the series inverse, used as is in float when
-//    kappa <= 0.11 (truncation below float rounding), else refined by Newton
-//    steps on G;
+//    kappa <= 0.11 (truncation below float rounding; through kappa^4 when
+//    every active lane of the wave has kappa <= 0.01), else refined by
+//    Newton steps on G;
 //  - larger kicks: Newton on G from the upper bound min(c = 0 solution,
 //    p0 + K/c), bracketed by bisection (G is monotone).
 // Newton stops when the step falls below a few ulps of |p| + c (the rounding
@@ -239,6 +249,10 @@ __device__ __forceinline__ T fast_advance(T c2, T p0, T K, int* iters = nullptr)
         const T s0 = Fm<T>::sqrt(p0 * p0 + c2);
         const T inv_s0 = Fm<T>::rcp(s0);
         const T kap = K * inv_s0 * inv_s0;
+        if (f32 && __all(kap <= T(0.01))) {  // the whole wave's kicks are small: four terms
+            if (iters) *iters += 1;
+            return p0 + s0 * series_inverse4(p0 * inv_s0, kap);
+        }
         pser = p0 + s0 * series_inverse(p0 * inv_s0, kap);
         if (f32 && kap <= T(0.11)) {
             if (iters) *iters += 1;

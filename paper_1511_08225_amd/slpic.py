@@ -71,7 +71,7 @@ class RunStatus(ctypes.Structure):
 class Tuning2D(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("margin", ctypes.c_int32), ("per_thread", ctypes.c_int32), ("tail_groups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("sort_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Status2D(ctypes.Structure):
@@ -444,8 +444,8 @@ class Mlp:
 class Sim2D:
     """One 2D3V sheath (y periodic over ny cells, dy = dx) on one GPU."""
 
-    def __init__(self, config: dict, ny: int, precision="f32", sort_every=8, tile=16, margin=0, per_thread=0,
-                 tail_groups=0, device="cuda"):
+    def __init__(self, config: dict, ny: int, precision="f32", sort_every=8, tile=8, margin=0, per_thread=0,
+                 tail_groups=0, sort_tile=0, device="cuda"):
         self.config = dict(config)
         self.nx, self.ny = int(config["nx"]), int(ny)
         self.precision = precision
@@ -453,7 +453,7 @@ class Sim2D:
         t = Tuning2D()
         t.precision = {"f32": SLPIC_F32, "f64": SLPIC_F64}[precision]
         t.sort_every, t.tile, t.margin = int(sort_every), int(tile), int(margin)
-        t.per_thread, t.tail_groups = int(per_thread), int(tail_groups)
+        t.per_thread, t.tail_groups, t.sort_tile = int(per_thread), int(tail_groups), int(sort_tile)
         self._tun = t
         L = lib()
         nbytes = L.slpic2d_workspace_bytes(ctypes.byref(self._cfg), self.ny, ctypes.byref(t))

@@ -83,7 +83,7 @@ def production_sheath(u_over_vti: float = 2.0, ppc: int = 1000, seed: int = 0, *
 PRODUCTION_U_SWEEP = (2.0, 5.0, 10.0, math.inf)
 
 
-def sheath2d(nx: int = 512, ny: int = 512, ppc: int = 64, u_over_vti: float = 3.0, tile: int = 16,
+def sheath2d(nx: int = 512, ny: int = 512, ppc: int = 64, u_over_vti: float = 3.0, tile: int = 8,
              sort_every: int = 8, seed: int = 0, **kw) -> dict:
     """A 2D3V sheath: the 1D geometry in x (symmetry plane at x = 0, wall at
     x = nx*dx, source in the first cells), periodic in y over ny cells with
