@@ -64,6 +64,35 @@ class _Steady(ctypes.Structure):
                 "window_mean": list(self.mean)}
 
 
+class _Wave(ctypes.Structure):
+    _fields_ = [("length", ctypes.c_double), ("v_phase", ctypes.c_double), ("phi_max", ctypes.c_double),
+                ("ramp_time", ctypes.c_double), ("qm", ctypes.c_double), ("dt", ctypes.c_double),
+                ("u", ctypes.c_double), ("beta_kind", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+def make_wave(w: dict) -> _Wave:
+    c = _Wave()
+    for k in ("length", "v_phase", "phi_max", "ramp_time", "qm", "dt", "u"):
+        setattr(c, k, float(w[k]))
+    c.beta_kind = _beta_kind(w.get("beta_kind", "step"))
+    return c
+
+
+def wave_push(w: dict, x, v, step0: int, nsteps: int):
+    """Advance test particles (arrays updated and returned as copies) through
+    the prescribed traveling wave for nsteps steps starting at step step0."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    v = np.array(v, dtype=np.float64, copy=True)
+    c = make_wave(w)
+    lib().orc_wave_push(ctypes.byref(c), _dp(x), _dp(v), len(x), int(step0), int(nsteps))
+    return x, v
+
+
+def wave_accel(w: dict, x: float, t: float) -> float:
+    c = make_wave(w)
+    return lib().orc_wave_accel(ctypes.byref(c), float(x), float(t))
+
+
 _lib = None
 
 _D = ctypes.c_double
@@ -119,6 +148,9 @@ def lib():
                                          _PD]),
             "orc_steady_init": (None, [ctypes.POINTER(_Steady), ctypes.c_int32, _D]),
             "orc_steady_feed": (None, [ctypes.POINTER(_Steady), _D, _I64]),
+            "orc_wave_phi0": (_D, [ctypes.POINTER(_Wave), _D]),
+            "orc_wave_accel": (_D, [ctypes.POINTER(_Wave), _D, _D]),
+            "orc_wave_push": (None, [ctypes.POINTER(_Wave), _PD, _PD, _I64, _I64, _I32]),
             "orc2_create": (_VP, [ctypes.POINTER(_Config), _I32, _I32]),
             "orc2_destroy": (None, [_VP]),
             "orc2_load": (None, [_VP]),

@@ -1279,3 +1279,46 @@ void orc2_get_grid(const orc2_run* r, double* Q0, double* Q1, double* phi, doubl
     if (Ex) memcpy(Ex, r->Ex, b);
     if (Ey) memcpy(Ey, r->Ey, b);
 }
+
+/* ======================================================================== */
+/* Test particles in a prescribed traveling wave (Sec. V, wave-particle     */
+/* interactions): 1D1V (v_y = v_z = 0), periodic x in [0, L), potential     */
+/* phi(x, t) = phi0(t) sin(k (x - v_phi t)), k = 2 pi / L, with phi0 rising   */
+/* linearly from 0 to phi_max over ramp_time and constant after (reading: a  */
+/* linear ramp; the paper says only that it rises slowly over twenty wave    */
+/* periods).  The field is evaluated exactly at (x^n, t^n = n dt); the       */
+/* particles do not act on it.  Each step is App. Eq. (A2a, A2b) with the    */
+/* exact velocity map and x wrapped into [0, L).                            */
+/* ======================================================================== */
+double orc_wave_phi0(const orc_wave* w, double t) {
+    if (!(w->ramp_time > 0.0) || t >= w->ramp_time) return w->phi_max;
+    return w->phi_max * (t / w->ramp_time);
+}
+
+/* acceleration (q/m) E_x with E_x = -dphi/dx */
+double orc_wave_accel(const orc_wave* w, double x, double t) {
+    double k = TWO_PI / w->length;
+    return -w->qm * orc_wave_phi0(w, t) * k * cos(k * (x - w->v_phase * t));
+}
+
+void orc_wave_push(const orc_wave* w, double* x, double* v, int64_t n, int64_t step0, int32_t nsteps) {
+    for (int64_t i = 0; i < n; ++i) {
+        double xi = x[i], vi = v[i];
+        for (int32_t s = 0; s < nsteps; ++s) {
+            double t = (double)(step0 + s) * w->dt;
+            double a[3] = {orc_wave_accel(w, xi, t), 0.0, 0.0};
+            double v0[3] = {vi, 0.0, 0.0}, v1[3];
+            orc_kick_exact(w->beta_kind, w->u, w->dt, v0, a, v1);
+            vi = v1[0];
+            double b = beta_of_s2(w->beta_kind, w->u, vi * vi);
+            xi = xi + b * vi * w->dt;
+            if (xi < 0.0 || xi >= w->length) {
+                xi = fmod(xi, w->length);
+                if (xi < 0.0) xi += w->length;
+                if (xi >= w->length) xi = 0.0;
+            }
+        }
+        x[i] = xi;
+        v[i] = vi;
+    }
+}

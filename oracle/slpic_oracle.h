@@ -131,6 +131,15 @@ void orc_set_counters(orc_run* r, int64_t step, double acc_e);
 void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E);
 void orc_get_steady(const orc_run* r, orc_steady* out);
 
+/* Test particles in a prescribed traveling wave (1D1V, periodic x). */
+typedef struct {
+    double length, v_phase, phi_max, ramp_time, qm, dt, u;
+    int32_t beta_kind, pad;
+} orc_wave;
+double orc_wave_phi0(const orc_wave* w, double t);
+double orc_wave_accel(const orc_wave* w, double x, double t);
+void orc_wave_push(const orc_wave* w, double* x, double* v, int64_t n, int64_t step0, int32_t nsteps);
+
 /* 2D3V (y periodic, dy = dx): nodes (i, j) at i*ny + j, i = 0..nx. */
 typedef struct orc2_run orc2_run;
 orc2_run* orc2_create(const orc_config* cfg, int32_t ny, int32_t tile);

@@ -96,6 +96,26 @@ def sheath2d(nx: int = 512, ny: int = 512, ppc: int = 64, u_over_vti: float = 3.
     return cfg
 
 
+def wave_test(v0_over_vphi: float, n: int = 100_000, seed: int = 0, cells: int = 100, periods_ramp: float = 20.0,
+              phi_max: float = 0.1, beta_kind: str = "step"):
+    """Test electrons in a prescribed traveling wave phi0(t) sin(k(x - v_phi t))
+    with v_phi = v_te = 1 in a periodic box of `cells` cells (dx = 1, k = 2 pi
+    / L), e phi_max / T_e = 0.1, phi0 ramped over 20 wave periods.  SLPIC
+    with speed limit v0 = v0_over_vphi * v_phi takes dt = dx / v0; v0 = inf
+    (PIC) takes dt = dx / (5 v_te).  Returns the wave description and the
+    initial particles: x uniform in [0, L), v a 1V Maxwellian at T_e = 1
+    (NumPy default_rng(seed))."""
+    L = float(cells)
+    u = math.inf if math.isinf(v0_over_vphi) else float(v0_over_vphi)
+    dt = 1.0 / 5.0 if math.isinf(u) else 1.0 / u
+    w = {"length": L, "v_phase": 1.0, "phi_max": phi_max, "ramp_time": periods_ramp * L, "qm": -1.0,
+         "dt": dt, "u": u, "beta_kind": beta_kind}
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, L, size=n)
+    v = rng.normal(0.0, 1.0, size=n)
+    return w, x, v
+
+
 def batched_sweep(nruns: int = 256, seed: int = 1, ppc_range=(200, 1000), cells_range=(128, 2048),
                   capacity_factor: float = 2.5, **kw) -> list[dict]:
     """Independent 1D sheaths: cells uniform in [128, 2048], ppc uniform in
