@@ -239,6 +239,36 @@ int slpic_velocity_map(int32_t precision, int32_t beta_kind, double u, double dt
 /* Release the context (not the caller's workspace).  Safe on NULL. */
 void slpic_destroy(void* ctx);
 
+/* ------------------------------------------------------------------------
+ * Test particles in a prescribed traveling wave (Sec. V, wave-particle
+ * interactions): 1D1V particles (v_y = v_z = 0) in the periodic box
+ * [0, length) under phi(x, t) = phi0(t) sin(k (x - v_phase t)),
+ * k = 2 pi / length, phi0 rising linearly from 0 to phi_max over
+ * [0, ramp_time] (0: phi_max from the start).  The particles do not act on
+ * the field.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double length;      /* periodic box [0, length)                          */
+    double v_phase;     /* phase velocity of the wave                        */
+    double phi_max;     /* potential amplitude after the ramp                */
+    double ramp_time;   /* duration of the linear ramp, >= 0                 */
+    double qm;          /* charge / mass of the particles (electrons: -1)    */
+    double dt;          /* time step                                         */
+    double u;           /* speed limit v0; +INFINITY: standard PIC           */
+    int32_t beta_kind;  /* SLPIC_BETA_STEP / SLPIC_BETA_SMOOTH               */
+    int32_t reserved;
+} slpic_wave_config;
+
+/* Advance n particles (caller device arrays d_x, d_v of float for SLPIC_F32
+ * or double for SLPIC_F64, updated in place: x in [0, length), v the
+ * velocity v^{n-1/2}) through steps step0 .. step0 + nsteps - 1: at step m,
+ * t = m dt, a = (q/m) E(x, t) with E = -dphi/dx evaluated at the particle,
+ * v <- the exact map of Eq. (A2a) (1V), x <- x + beta(|v|) v dt wrapped into
+ * [0, length).  One thread per particle carries it through all nsteps in
+ * registers.  Async on stream; SLPIC_EINVAL on bad arguments. */
+int slpic_wave_push(int32_t precision, const slpic_wave_config* cfg, void* d_x, void* d_v, int64_t n,
+                    int64_t step0, int32_t nsteps, void* stream);
+
 /* Static description of an SLPIC_* code. */
 const char* slpic_strerror(int code);
 

@@ -31,6 +31,7 @@ UNITS = {
     "kernels2d_f64.hip": ["-ffp-contract=off"],
     "field2d.hip": ["-ffp-contract=off"],
     "api2d.cpp": ["-x", "hip"],
+    "wave.hip": ["-ffp-contract=off"],
 }
 
 

@@ -120,9 +120,9 @@ __device__ __forceinline__ T beta_s2(T s2, T u, T u2, bool uinf) {
 }
 
 // beta of Eq. (11a)/(11b) in FP64 from the stored particle velocity, for the
-// charge of injected particles and the moments (float particles: hardware
-// reciprocal square root plus one Newton step, ~1e-13; double particles: the
-// correctly rounded form).
+// charge deposit, injected particles and the moments (float particles: the
+// float hardware reciprocal square root refined by one FP64 Newton step,
+// ~1e-14; double particles: the correctly rounded form).
 template <int BK, typename T>
 __device__ __forceinline__ double beta_deposit(T vx, T c2, double u, double u2, bool uinf) {
     if (uinf) return 1.0;
@@ -131,7 +131,8 @@ __device__ __forceinline__ double beta_deposit(T vx, T c2, double u, double u2, 
     if (BK == kBetaSmooth) return 1.0 / sqrt(1.0 + s2 / u2);
     if (s2 <= u2) return 1.0;
     if (sizeof(T) == 8) return u / sqrt(s2);
-    double y = __builtin_amdgcn_rsq(s2);
+    // float seed (~1e-7), one Newton step in FP64: ~1.5e-14, always from below
+    double y = (double)__builtin_amdgcn_rsqf((float)s2);
     y = y * (1.5 - 0.5 * s2 * y * y);
     return u * y;
 }

@@ -68,6 +68,12 @@ class RunStatus(ctypes.Structure):
                 "window_mean": list(self.window_mean), "moment_samples": self.moment_samples}
 
 
+class WaveConfig(ctypes.Structure):
+    _fields_ = [("length", ctypes.c_double), ("v_phase", ctypes.c_double), ("phi_max", ctypes.c_double),
+                ("ramp_time", ctypes.c_double), ("qm", ctypes.c_double), ("dt", ctypes.c_double),
+                ("u", ctypes.c_double), ("beta_kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Tuning2D(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("margin", ctypes.c_int32), ("per_thread", ctypes.c_int32), ("tail_groups", ctypes.c_int32),
@@ -133,6 +139,7 @@ def lib():
             "slpic_profile_read": (ctypes.c_int, [_P, _PD, _PI64]),
             "slpic_total_slots": (ctypes.c_int, [_P, _PI64]),
             "slpic_destroy": (None, [_P]),
+            "slpic_wave_push": (ctypes.c_int, [i32, ctypes.POINTER(WaveConfig), _P, _P, i64, i64, i32, _P]),
             "slpic2d_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(RunConfig), i32,
                                                           ctypes.POINTER(Tuning2D)]),
             "slpic2d_init": (ctypes.c_int, [ctypes.POINTER(RunConfig), i32, ctypes.POINTER(Tuning2D), _P,
@@ -205,6 +212,24 @@ def tuning(precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0, grap
 
 def _dp(a: np.ndarray):
     return a.ctypes.data_as(_PD)
+
+
+def wave_push(w: dict, x: torch.Tensor, v: torch.Tensor, step0: int, nsteps: int):
+    """Advance test particles (device tensors, float32 or float64, updated in
+    place) through the prescribed traveling wave described by `w` (length,
+    v_phase, phi_max, ramp_time, qm, dt, u, beta_kind)."""
+    if x.dtype != v.dtype or x.shape != v.shape or not x.is_contiguous() or not v.is_contiguous():
+        raise SlpicError("x and v must be contiguous tensors of one shape and dtype")
+    prec = {torch.float32: SLPIC_F32, torch.float64: SLPIC_F64}.get(x.dtype)
+    if prec is None:
+        raise SlpicError("x and v must be float32 or float64")
+    c = WaveConfig()
+    for k in ("length", "v_phase", "phi_max", "ramp_time", "qm", "dt", "u"):
+        setattr(c, k, float(w[k]))
+    c.beta_kind = _beta_kind(w.get("beta_kind", "step"))
+    stream = _P(torch.cuda.current_stream(x.device).cuda_stream)
+    _check(lib().slpic_wave_push(prec, ctypes.byref(c), _P(x.data_ptr()), _P(v.data_ptr()), x.numel(), int(step0),
+                                 int(nsteps), stream), "slpic_wave_push")
 
 
 class Sim:
