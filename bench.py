@@ -434,6 +434,45 @@ def run_2d(args, steps: int = 256, warmup: int = 64) -> dict:
     return out
 
 
+def run_wave(args, n: int = 4_194_304, steps: int = 4000, per_launch: int = 500) -> dict:
+    """Test electrons in the prescribed traveling wave (the paper's
+    wave-particle test) at v0 = 2 v_phi, FP32: pushes/s of slpic_wave_push
+    (each launch carries every particle through `per_launch` steps in
+    registers), timed with events on the launch stream, and the oracle on a
+    bounded sample."""
+    import torch
+    import numpy as np
+    import workloads
+    from paper_1511_08225_amd import slpic
+    w, x0, v0 = workloads.wave_test(2.0, n=n, seed=0)
+    x = torch.tensor(x0.astype(np.float32), device="cuda")
+    v = torch.tensor(v0.astype(np.float32), device="cuda")
+    slpic.wave_push(w, x, v, 0, per_launch)  # warm-up launch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    done = per_launch
+    while done < per_launch + steps:
+        slpic.wave_push(w, x, v, done, per_launch)
+        done += per_launch
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"metric": "test-particle pushes/s (prescribed traveling wave)", "value": n * steps / (ms * 1e-3),
+           "unit": "particle-pushes/s", "steps": steps, "particles": n, "ms_per_step": ms / steps, "dtype": "f32",
+           "config": {"workload": f"1D1V electrons, v_phi = v_te, e phi_max/T_e = 0.1, v0 = 2 v_phi, dt = dx/v0, "
+                                  f"{per_launch} steps per launch"}}
+    if not args.no_cpu_baseline:
+        import oracle
+        m = 20000
+        t0 = time.perf_counter()
+        oracle.wave_push(w, x0[:m], v0[:m], 0, 100)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m * 100 / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{m} particles x 100 steps of the same workload, FP64 C oracle, one thread"}
+    return out
+
+
 def launch_params(cfg, args) -> dict:
     """Push chunk, workgroup size, sort period and bucket: from the autotuner
     (cached per workload signature) unless given on the command line."""
@@ -492,6 +531,8 @@ def main() -> int:
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--only-2d", action="store_true", help="the 2D3V sheath line alone, and exit")
     ap.add_argument("--no-2d", action="store_true", help="leave out the 2D3V sheath measurement")
+    ap.add_argument("--only-wave", action="store_true", help="the wave-particle test-particle line alone, and exit")
+    ap.add_argument("--no-wave", action="store_true", help="leave out the wave-particle measurement")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the counter workload (copy calibration + direct-launch steps) and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -518,6 +559,9 @@ def main() -> int:
         return 2
     if args.only_2d:
         print(json.dumps(run_2d(args, args.steps, args.warmup)), flush=True)
+        return 0
+    if args.only_wave:
+        print(json.dumps(run_wave(args)), flush=True)
         return 0
 
     import workloads
@@ -582,6 +626,8 @@ def main() -> int:
                                "traffic": traffic_for(10 * args.ppc, params10["chunk"])}
     if not args.no_2d:
         line["sheath_2d"] = run_2d(args)
+    if not args.no_wave:
+        line["wave_test"] = run_wave(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)
