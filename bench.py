@@ -211,8 +211,9 @@ def _to_steady(sim, nruns, max_steps, block):
 
 def steady_bench(args) -> int:
     """Wall time to the steady sheath (wall-potential detector) from cold
-    loads: all runs batched in one context, and the same runs one at a time
-    (a subset, the first --plain-runs)."""
+    loads: all runs batched in one context, each run retired (frozen) by the
+    library from the step after its detector flags it, and the same runs one
+    at a time (a subset, the first --plain-runs), each stopped when flagged."""
     import workloads
     from paper_1511_08225_amd import autotune, slpic
     cfgs = workloads.batched_sweep(nruns=args.runs, seed=1)
@@ -221,12 +222,12 @@ def steady_bench(args) -> int:
     block = g * max(1, 256 // g)
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
               chunk=params["chunk"], block=params["block"], graph_steps=g)
-    sim = slpic.Sim(cfgs, **kw)
+    sim = slpic.Sim(cfgs, retire_steady=True, **kw)
     b_steady, b_seen, b_total, b_steps, b_err = _to_steady(sim, len(cfgs), args.max_steps, block)
     sim.close()
     plain = []
     for r in range(min(args.plain_runs, len(cfgs))):
-        one = slpic.Sim([dict(cfgs[r], run=0)], **kw)
+        one = slpic.Sim([cfgs[r]], **kw)  # same run id: the same realisation as in the batch
         s1, seen1, tot1, steps1, err1 = _to_steady(one, 1, args.max_steps, block)
         one.close()
         plain.append({"run": r, "steady_step": s1[0], "seconds": seen1[0] if seen1[0] is not None else tot1,
@@ -236,6 +237,7 @@ def steady_bench(args) -> int:
     print(json.dumps({
         "metric": "time-to-steady-sheath, batched vs plain (cold start)", "unit": "s",
         "runs": len(cfgs), "max_steps": args.max_steps, "block_steps": block, "tuned": params,
+        "batched_mode": "one context, steady runs retired (slpic_tuning.retire_steady)",
         "batched": {"seconds_all": b_total, "steps": b_steps, "reached": n_b,
                     "seconds_median_run": sorted(s for s in b_seen if s is not None)[n_b // 2] if n_b else None,
                     "steady_steps": b_steady, "error_runs": [r for r, e in enumerate(b_err) if e]},
@@ -522,7 +524,7 @@ def main() -> int:
     ap.add_argument("--sweep", action="store_true", help="batched-sweep throughput (autotuned) and exit")
     ap.add_argument("--runs", type=int, default=256, help="runs in the batched sweep")
     ap.add_argument("--steady", action="store_true", help="time to the steady sheath, batched vs plain, and exit")
-    ap.add_argument("--plain-runs", type=int, default=16, help="runs timed one at a time in --steady")
+    ap.add_argument("--plain-runs", type=int, default=32, help="runs timed one at a time in --steady")
     ap.add_argument("--max-steps", type=int, default=16384, help="step cap in --steady")
     ap.add_argument("--warm", action="store_true", help="learned warm start end to end, and exit")
     ap.add_argument("--train-runs", type=int, default=512)

@@ -110,7 +110,9 @@ typedef struct {
                           /* wavefront per chunk; 0 = default (128)                  */
     int32_t graph_steps;  /* steps captured per HIP graph; 0 = direct launches       */
     int32_t sort_tile;    /* particles per sort workgroup; 0 = default               */
-    int32_t reserved;
+    int32_t retire_steady;/* 1: a run stops advancing (push, source, field solve and */
+                          /* step count frozen) from the step after its steady      */
+                          /* detector flags it; 0 = every run always advances       */
 } slpic_tuning;
 
 typedef struct {

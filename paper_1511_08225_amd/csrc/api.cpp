@@ -146,7 +146,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (tin) t = *tin;
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
     if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
-        t.sort_tile < 0)
+        t.sort_tile < 0 || (t.retire_steady != 0 && t.retire_steady != 1))
         return SLPIC_EINVAL;
     if (t.block == 0) t.block = 128;
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
@@ -225,6 +225,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         if (c.steady_window < 0 || !(c.steady_tol >= 0.0)) return SLPIC_EINVAL;
         R.steady_window = c.steady_window > 0 ? c.steady_window : std::max(1, c.nx / 4);
         R.steady_tol = c.steady_tol > 0.0 ? c.steady_tol : 0.02;
+        R.retire = t.retire_steady ? 1 : 0;
         R.goff = goff;
         goff += R.nodes;
         P.max_nodes = std::max(P.max_nodes, R.nodes);

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(KArgs a, int advance) {
 __global__ __launch_bounds__(kFieldThreads) void k_field_step(KArgs a) {
     const int run = blockIdx.x;
     RunState* st = a.state + run;
+    if (retired(a.runs[run], *st)) return;  // frozen once steady (workgroup-uniform)
     if (threadIdx.x == 0) {
         const InjectPlan& ip = a.inj[run];
         for (int s = 0; s < kMaxSpecies; ++s) {

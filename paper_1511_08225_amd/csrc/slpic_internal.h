@@ -39,6 +39,8 @@ struct RunInfo {
     int32_t nchunk[kMaxSpecies]; // push chunks of (run, species)
     int32_t steady_window;       // steps per wall-potential window
     int32_t warm;                // 1: loaded from predicted profiles (k_load_warm), not cold
+    int32_t retire;              // 1: frozen once steady (steady_step >= 0)
+    int32_t pad_r;
     double steady_tol;           // relative spread of three window means that counts as steady
 };
 
@@ -60,6 +62,12 @@ struct alignas(64) RunState {
     int64_t steady_step;         // step count when first steady, -1 before
     int64_t msamples;            // moment samples in the window accumulator
 };
+
+// A run frozen under retire_steady: once its steady detector has flagged it,
+// no push, source, field solve or step count.
+__host__ __device__ inline bool retired(const RunInfo& R, const RunState& st) {
+    return R.retire != 0 && st.steady_step >= 0;
+}
 
 // Source bookkeeping of one step, computed from the push counters before the
 // new particles are written and applied to the run state after.

@@ -343,3 +343,51 @@ def test_capacity_overflow_sets_sticky_flag(gpu_lib):
     assert st["error_flags"] & gpu_lib.FLAG_CAPACITY
     assert st["nslots"][1] == st["capacity"][1]
     assert np.isfinite(st["wall_potential"])
+
+
+def _live_sorted(parts):
+    x, vx, vp = parts
+    live = x >= 0
+    m = np.stack([x[live], vx[live], vp[live]], axis=1)
+    return m[np.lexsort((m[:, 2], m[:, 1], m[:, 0]))]
+
+
+def test_retired_runs_freeze_at_their_steady_step(gpu_lib):
+    """retire_steady: a run stops advancing once its detector has flagged it
+    (its grid, particles and step count stay as at the flagged step) while the
+    other runs of the context go on exactly as in a context that never
+    retires."""
+    cfgs = [workloads.sheath(nx=32, ppc=40, u_over_vti=3.0, dt=5.0, seed=s, run=r, steady_window=8,
+                             steady_tol=0.5, sort_every=16) for r, s in enumerate((1, 2, 3))]
+    sim = gpu_lib.Sim(cfgs, precision="f64", sort_every=16, retire_steady=True)
+    ref = gpu_lib.Sim(cfgs, precision="f64", sort_every=16)
+    flagged, snap = {}, {}
+    for k in range(400):
+        sim.step(1)
+        ref.step(1)
+        st = sim.status()
+        for r in range(3):
+            if r not in flagged and st[r]["steady_step"] >= 0:
+                flagged[r] = st[r]["steady_step"]
+                snap[r] = ref.grid(r)
+        if len(flagged) == 3:
+            break
+    print_case(f"retire: steady steps {flagged}")
+    assert len(flagged) == 3 and len(set(flagged.values())) > 1
+    frozen = {r: (sim.grid(r), [sim.export_particles(r, s) for s in range(2)]) for r in range(3)}
+    sim.step(40)  # crosses sorts
+    st = sim.status()
+    for r in range(3):
+        assert st[r]["step"] == flagged[r] == st[r]["steady_step"]
+        g = sim.grid(r)
+        for key in ("Q", "phi", "E"):
+            assert np.array_equal(g[key], frozen[r][0][key]), (r, key)
+        for s in range(2):  # the same live particles (a sort may compact and reorder them)
+            a = _live_sorted(sim.export_particles(r, s))
+            b = _live_sorted(frozen[r][1][s])
+            assert np.array_equal(a, b), (r, s)
+        # the run's frozen state is the never-retired context's state at that step
+        for s in range(2):
+            assert rel_inf(g["Q"][s], snap[r]["Q"][s]) <= 1e-12, (r, s)
+    sim.close()
+    ref.close()
