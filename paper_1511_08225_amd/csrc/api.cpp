@@ -124,7 +124,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
-        totals, counts, push_err, Macc, inj, btot, history, total;
+        totals, counts, push_err, Macc, btot, history, total;
 };
 
 struct Plan {
@@ -283,7 +283,6 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.counts = take(sizeof(int2) * kMaxSpecies * kCountSlots * nruns);
     L.push_err = take(sizeof(int) * nruns);
     L.Macc = take(sizeof(double) * 7 * P.total_nodes);
-    L.inj = take(sizeof(InjectPlan) * nruns);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
     L.total = o;
@@ -308,7 +307,7 @@ struct Context {
     unsigned char* ws = nullptr;
     long long* btot = nullptr;
     int64_t steps_done = 0;
-    size_t push_lds = 0, field_lds = 0, sort_lds = 0, inject_lds = 0, moments_lds = 0;
+    size_t push_lds = 0, field_lds = 0, source_field_lds = 0, sort_lds = 0, moments_lds = 0;
     hipGraphExec_t gexec = nullptr;
     int graph_len = 0;
     bool prof = false;
@@ -355,13 +354,12 @@ void l_push(Context* c, bool push, hipStream_t s) {
     else
         launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, s);
 }
-constexpr int kInjectGroups = 8;  // workgroups per run generating source particles
-void l_inject(Context* c, hipStream_t s) {
-    if (prec(c) == SLPIC_F32) launch_inject_f32(c->a, c->P.nruns, kInjectGroups, c->inject_lds, s);
-    else launch_inject_f64(c->a, c->P.nruns, kInjectGroups, c->inject_lds, s);
+void l_source_field(Context* c, hipStream_t s) {
+    if (prec(c) == SLPIC_F32) launch_source_field_f32(c->a, c->P.nruns, c->source_field_lds, s);
+    else launch_source_field_f64(c->a, c->P.nruns, c->source_field_lds, s);
 }
 
-// timed launch wrapper: class k in {0 push, 1 inject, 2 field, 3 sort}
+// timed launch wrapper: class k in {0 push, 1 source (inside the field launch), 2 field, 3 sort}
 template <typename F>
 int timed(Context* c, int k, hipStream_t s, F&& f) {
     if (!c->prof || !((c->prof_mask >> k) & 1)) {
@@ -407,8 +405,7 @@ int do_sort(Context* c, hipStream_t s) {
 int one_step(Context* c, int64_t local_step, hipStream_t s) {
     int rc;
     if ((rc = timed(c, 0, s, [&] { l_push(c, true, s); }))) return rc;
-    if ((rc = timed(c, 1, s, [&] { l_inject(c, s); }))) return rc;
-    if ((rc = timed(c, 2, s, [&] { launch_field_step(c->a, c->P.nruns, c->field_lds, s); }))) return rc;
+    if ((rc = timed(c, 2, s, [&] { l_source_field(c, s); }))) return rc;
     const int se = c->P.tun.sort_every;
     if (se > 0 && (local_step + 1) % se == 0)
         if ((rc = do_sort(c, s))) return rc;
@@ -534,16 +531,15 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.counts = (int2*)(w + L.counts);
     a.push_err = (int*)(w + L.push_err);
     a.Macc = (double*)(w + L.Macc);
-    a.inj = (InjectPlan*)(w + L.inj);
     a.history = (double*)(w + L.history);
     c->btot = (long long*)(w + L.btot);
     const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
     c->push_lds = (size_t)c->P.max_nodes * (8 + tsz) + 16;
     c->field_lds = (size_t)c->P.max_nodes * 8 + 32 * 8;
     c->sort_lds = (size_t)4 * c->P.max_nkeys * sizeof(int);
-    c->inject_lds = (size_t)2 * c->P.max_src * 8;
+    c->source_field_lds = c->field_lds + (size_t)2 * c->P.max_src * 8;
     c->moments_lds = (size_t)3 * c->P.max_nodes * 8;
-    if (c->push_lds > 65536 || c->sort_lds > 65536 || c->moments_lds > 65536) {
+    if (c->push_lds > 65536 || c->sort_lds > 65536 || c->moments_lds > 65536 || c->source_field_lds > 65536) {
         delete c;
         return SLPIC_EINVAL;
     }

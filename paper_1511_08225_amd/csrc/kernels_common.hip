@@ -43,33 +43,6 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(KArgs a, int advance) {
     field_solve(a, blockIdx.x, advance, D, D + a.runs[blockIdx.x].nodes);
 }
 
-// The step's field kernel: apply the source bookkeeping and the push error
-// flags of the step to the run state, clear the push counters, then solve
-// for phi^{n+1}, E^{n+1}.
-__global__ __launch_bounds__(kFieldThreads) void k_field_step(KArgs a) {
-    const int run = blockIdx.x;
-    RunState* st = a.state + run;
-    if (retired(a.runs[run], *st)) return;  // frozen once steady (workgroup-uniform)
-    if (threadIdx.x == 0) {
-        const InjectPlan& ip = a.inj[run];
-        for (int s = 0; s < kMaxSpecies; ++s) {
-            st->nslots[s] = ip.base[s] + ip.count[s];
-            st->injected_total[s] += ip.count[s];
-            st->absorbed_total[s] += ip.absorbed[s];
-        }
-        st->pushed_total += ip.pushed;
-        st->acc_e = ip.acc_e;
-        if (ip.overflow) st->error |= 1;
-        st->error |= a.push_err[run];
-        a.push_err[run] = 0;
-    }
-    int2* cs = a.counts + (int64_t)run * kMaxSpecies * kCountSlots;
-    for (int j = threadIdx.x; j < kMaxSpecies * kCountSlots; j += blockDim.x) cs[j] = make_int2(0, 0);
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* D = (double*)smem;
-    field_solve(a, run, 1, D, D + a.runs[run].nodes);
-}
-
 // Exclusive scan of the sort histogram, in place, over all (run, species)
 // segments at once: block sums, a scan of the block sums, then each block
 // rescanned with its offset.  A segment's first entry is then its base and
@@ -188,9 +161,6 @@ void launch_init_state(const KArgs& a, int nruns, hipStream_t s) {
 }
 void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL(k_field, dim3(nruns), dim3(kFieldThreads), lds, s, a, advance);
-}
-void launch_field_step(const KArgs& a, int nruns, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_field_step, dim3(nruns), dim3(kFieldThreads), lds, s, a);
 }
 int scan_blocks(int64_t n) { return (int)((n + kScanBlock - 1) / kScanBlock); }
 void launch_scan_ints(int* h, int64_t n, long long* btot, hipStream_t s) {

@@ -15,7 +15,7 @@ namespace slpic {
     void launch_velocity_map_##sfx(int beta_kind, double u, double dt, int64_t n, const void* vx,      \
                                    const void* c2, const void* acc, void* out, int* iters,             \
                                    hipStream_t s);                                                     \
-    void launch_inject_##sfx(const KArgs& a, int nruns, int groups, size_t lds, hipStream_t s);         \
+    void launch_source_field_##sfx(const KArgs& a, int nruns, size_t lds, hipStream_t s);              \
     void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \
                               double* out, int per_run, hipStream_t s);                                \
     void launch_sort_hist_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);     \
@@ -28,7 +28,6 @@ SLPIC_DECLARE_LAUNCHERS(f64)
 // precision-independent kernels
 void launch_init_state(const KArgs& a, int nruns, hipStream_t s);
 void launch_field(const KArgs& a, int nruns, int advance, size_t lds, hipStream_t s);
-void launch_field_step(const KArgs& a, int nruns, size_t lds, hipStream_t s);
 int scan_blocks(int64_t hist_entries);
 void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s);
 // exclusive scan of n ints in place; btot[scan_blocks(n)] receives the total

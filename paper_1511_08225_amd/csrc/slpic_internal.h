@@ -69,18 +69,6 @@ __host__ __device__ inline bool retired(const RunInfo& R, const RunState& st) {
     return R.retire != 0 && st.steady_step >= 0;
 }
 
-// Source bookkeeping of one step, computed from the push counters before the
-// new particles are written and applied to the run state after.
-struct InjectPlan {
-    int64_t base[kMaxSpecies];      // first new slot
-    int64_t count[kMaxSpecies];     // particles injected
-    int64_t absorbed[kMaxSpecies];  // particles absorbed at the wall this step
-    int64_t pushed;                 // live particles pushed this step
-    double acc_e;                   // carried fraction after this step
-    int32_t overflow;               // capacity hit
-    int32_t pad;
-};
-
 // One cell of a warm load: `count` particles of (run, species) at slots
 // start.., drawn from a Maxwellian drifting at V along x, as f/beta.
 struct WarmCell {
@@ -130,7 +118,6 @@ struct KArgs {
     int64_t* totals;      // live slots after the sort [run][species]
     int2* counts;         // [run][species][kCountSlots]: (absorbed, pushed) of the last push
     int* push_err;        // [run]: error flags raised by the last push
-    struct InjectPlan* inj;  // [run]: source counts of the current step
     int32_t* perm;        // last sort's permutation (new slot -> old slot)
     double* Macc;         // moment window accumulators [run]: 7 rows of nodes at 7*goff
 };
