@@ -24,6 +24,7 @@ _SRC = os.path.join(_HERE, "slpic_oracle.c")
 _LIB = os.path.join(_HERE, "libslpic_oracle.so")
 
 BETA_STEP, BETA_SMOOTH = 0, 1
+GEOM_SHEATH, GEOM_PLATES = 0, 1
 KICK_EXACT, KICK_MMP = 0, 1
 
 
@@ -51,7 +52,8 @@ class _Config(ctypes.Structure):
                 ("sort_every", ctypes.c_int32), ("sort_bucket", ctypes.c_int32),
                 ("kick", ctypes.c_int32), ("mmp_tol", ctypes.c_double),
                 ("capacity_factor", ctypes.c_double), ("steady_window", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("steady_tol", ctypes.c_double)]
+                ("pad", ctypes.c_int32), ("steady_tol", ctypes.c_double), ("geometry", ctypes.c_int32),
+                ("pad2", ctypes.c_int32), ("bias", ctypes.c_double)]
 
 
 class _Steady(ctypes.Structure):
@@ -122,6 +124,10 @@ def lib():
             "orc_inject_particle": (None, [ctypes.POINTER(_Config), _I32, ctypes.c_uint32,
                                            ctypes.c_uint32, _PD]),
             "orc_poisson1d": (None, [_I32, _D, _PD, _PD, _PD]),
+            "orc_poisson1d_plates": (None, [_I32, _D, _PD, _D, _PD, _PD]),
+            "orc_wall_inject_particle": (None, [ctypes.POINTER(_Config), _I32, ctypes.c_uint32, ctypes.c_uint32,
+                                                _PD]),
+            "orc_wall_flux_per_step": (_D, [ctypes.POINTER(_Config), _I32]),
             "orc_create": (_VP, [ctypes.POINTER(_Config)]),
             "orc_destroy": (None, [_VP]),
             "orc_load": (None, [_VP]),
@@ -214,6 +220,8 @@ def make_config(cfg: dict) -> _Config:
     c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
     c.steady_window = int(cfg.get("steady_window", 0))
     c.steady_tol = float(cfg.get("steady_tol", 0.0))
+    c.geometry = {"sheath": GEOM_SHEATH, "plates": GEOM_PLATES}[cfg.get("geometry", "sheath")]
+    c.bias = float(cfg.get("bias", 0.0))
     return c
 
 
@@ -314,6 +322,25 @@ def poisson1d(nx: int, dx: float, Q: np.ndarray):
     E = np.zeros(nx + 1)
     lib().orc_poisson1d(nx, dx, _dp(Q), _dp(phi), _dp(E))
     return phi, E
+
+
+def poisson1d_plates(nx: int, dx: float, Q: np.ndarray, bias: float):
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    phi, E = np.zeros(nx + 1), np.zeros(nx + 1)
+    lib().orc_poisson1d_plates(nx, dx, _dp(Q), float(bias), _dp(phi), _dp(E))
+    return phi, E
+
+
+def wall_inject_particle(cfg: dict, s: int, k: int, step: int) -> np.ndarray:
+    c = make_config(cfg)
+    out = np.zeros(4)
+    lib().orc_wall_inject_particle(ctypes.byref(c), s, k, step, _dp(out))
+    return out
+
+
+def wall_flux_per_step(cfg: dict, s: int) -> float:
+    c = make_config(cfg)
+    return lib().orc_wall_flux_per_step(ctypes.byref(c), s)
 
 
 # ----------------------------------------------------------------------- run

@@ -451,6 +451,68 @@ void orc_poisson1d(int32_t nx, double dx, const double* Q, double* phi, double* 
     free(dp);
 }
 
+/* Poisson with two conducting plates (Sec. IV): phi_0 = 0, phi_nx = bias,   */
+/* the interior rows of the three-point stencil solved by the Thomas         */
+/* algorithm; E by centred differences inside and one-sided second-order     */
+/* differences at both plates.                                              */
+void orc_poisson1d_plates(int32_t nx, double dx, const double* Q, double bias, double* phi, double* E) {
+    int n = nx - 1; /* unknowns phi_1..phi_{nx-1} */
+    double* cp = (double*)malloc(sizeof(double) * (size_t)n);
+    double* dp = (double*)malloc(sizeof(double) * (size_t)n);
+    double dx2 = dx * dx;
+    for (int k = 0; k < n; ++k) {
+        int j = k + 1;
+        double rhs = (Q[j] / dx) * dx2;
+        if (j == nx - 1) rhs += bias;  /* phi_nx = bias moves to the right-hand side */
+        double a = (k == 0) ? 0.0 : -1.0, b = 2.0, c = (k == n - 1) ? 0.0 : -1.0;
+        if (k == 0) {
+            cp[0] = c / b;
+            dp[0] = rhs / b;
+        } else {
+            double m = b - a * cp[k - 1];
+            cp[k] = c / m;
+            dp[k] = (rhs - a * dp[k - 1]) / m;
+        }
+    }
+    phi[0] = 0.0;
+    phi[nx] = bias;
+    phi[n] = dp[n - 1];
+    for (int k = n - 2; k >= 0; --k) phi[k + 1] = dp[k] - cp[k] * phi[k + 2];
+    E[0] = -(-3.0 * phi[0] + 4.0 * phi[1] - phi[2]) / (2.0 * dx);
+    for (int j = 1; j < nx; ++j) E[j] = -(phi[j + 1] - phi[j - 1]) / (2.0 * dx);
+    E[nx] = -(3.0 * phi[nx] - 4.0 * phi[nx - 1] + phi[nx - 2]) / (2.0 * dx);
+    free(cp);
+    free(dp);
+}
+
+/* Expected g-particles entering through the plate at x = L per step: the
+ * one-sided flux n0 v_t / sqrt(2 pi) of a stationary Maxwellian (n0 = 1)
+ * times dt, over the weight (each entering g-particle carries w physical
+ * particles across the plate: its flux beta v g equals v f, Eq. 5). */
+double orc_wall_flux_per_step(const orc_config* cfg, int s) {
+    return species_vt(cfg, s) / sqrt(TWO_PI) * cfg->dt / orc_weight(cfg, s);
+}
+
+/* Particle k entering through the plate at x = L in step `step`: v_x from
+ * the flux-weighted half Maxwellian (v_x = -v_t sqrt(-2 ln(1 - U))), v_y, v_z
+ * Maxwellian, and a position a uniform fraction of this step's travel
+ * beta(|v|) |v_x| dt inside the plate (held within source_cells). */
+void orc_wall_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step, double out[4]) {
+    orc_stream st;
+    stream_init(&st, cfg, k, step, ORC_PURPOSE_WALL, s);
+    double vt = species_vt(cfg, s);
+    double vx = -vt * sqrt(-2.0 * log(1.0 - stream_next(&st)));
+    double z[3];
+    stream_normal3(&st, z);
+    double vy = vt * z[0], vz = vt * z[1];
+    double s2 = vx * vx + (vy * vy + vz * vz);
+    double depth = beta_of_s2(cfg->beta_kind, cfg->u, s2) * fabs(vx) * cfg->dt / cfg->dx * stream_next(&st);
+    if (depth > (double)cfg->source_cells) depth = (double)cfg->source_cells;
+    double x = (double)cfg->nx - depth;
+    if (x >= (double)cfg->nx) x = nextafter((double)cfg->nx, 0.0);
+    out[0] = x; out[1] = vx; out[2] = vy; out[3] = vz;
+}
+
 /* ------------------------------------------------------------------------ */
 /* A run: particle slots (dead slots have xt < 0 until compaction), grids.   */
 /* ------------------------------------------------------------------------ */
@@ -492,6 +554,7 @@ struct orc_run {
     double *x[2], *vx[2], *vy[2], *vz[2];
     double *Q[2], *phi, *E;
     double acc_e;
+    double acc_flux[2];  /* plates: fractional g-particles carried per species */
     int64_t step;
     int64_t absorbed_total[2], injected_total[2];
 };
@@ -562,7 +625,10 @@ static void solve_fields(orc_run* r) {
     double* Qt = (double*)calloc((size_t)nodes, sizeof(double));
     for (int j = 0; j < nodes; ++j)
         for (int s = 0; s < r->cfg.nspecies; ++s) Qt[j] += r->Q[s][j];
-    orc_poisson1d(r->cfg.nx, r->cfg.dx, Qt, r->phi, r->E);
+    if (r->cfg.geometry == ORC_GEOM_PLATES)
+        orc_poisson1d_plates(r->cfg.nx, r->cfg.dx, Qt, r->cfg.bias, r->phi, r->E);
+    else
+        orc_poisson1d(r->cfg.nx, r->cfg.dx, Qt, r->phi, r->E);
     free(Qt);
 }
 
@@ -617,7 +683,7 @@ void orc_sort(orc_run* r, int32_t* perm0, int32_t* perm1) {
 
 void orc_load(orc_run* r) {
     for (int s = 0; s < r->cfg.nspecies; ++s) {
-        int64_t n0 = (int64_t)r->cfg.nx * r->cfg.species[s].ppc;
+        int64_t n0 = r->cfg.geometry == ORC_GEOM_PLATES ? 0 : (int64_t)r->cfg.nx * r->cfg.species[s].ppc;
         ensure_capacity(r, s, n0);
         for (int64_t i = 0; i < n0; ++i) {
             double p[4];
@@ -628,6 +694,7 @@ void orc_load(orc_run* r) {
     }
     r->step = 0;
     r->acc_e = 0.0;
+    r->acc_flux[0] = r->acc_flux[1] = 0.0;
     if (r->cfg.sort_every > 0) orc_sort(r, NULL, NULL);
     orc_refresh_fields(r);
 }
@@ -770,6 +837,14 @@ static void inject(orc_run* r, int s, int64_t count) {
     r->injected_total[s] += count;
 }
 
+/* The potential the steady detector watches: Phi_w = phi(0) - phi(L) for
+ * the sheath; for the plates, whose end potentials are fixed, phi at the
+ * mid-plane node. */
+static double orc_monitor_potential(const orc_run* r) {
+    if (r->cfg.geometry == ORC_GEOM_PLATES) return r->phi[r->cfg.nx / 2];
+    return r->phi[0] - r->phi[r->cfg.nx];
+}
+
 /* One step of Eq. (A2a-d). */
 void orc_step(orc_run* r, int32_t nsteps) {
     const orc_config* cfg = &r->cfg;
@@ -794,14 +869,19 @@ void orc_step(orc_run* r, int32_t nsteps) {
                 /* Eq. (A2b): x^{n+1} = x^n + beta(|v^{n+1/2}|) v^{n+1/2} dt */
                 double b = beta_of_s2(cfg->beta_kind, cfg->u, norm2(v1));
                 double xn = xt + b * v1[0] * dtdx;
-                if (xn < 0.0) { /* symmetry plane: specular reflection */
-                    xn = -xn;
-                    v1[0] = -v1[0];
+                int left_out = 0;
+                if (xn < 0.0) {
+                    if (cfg->geometry == ORC_GEOM_PLATES) {
+                        left_out = 1; /* absorbing plate */
+                    } else {      /* symmetry plane: specular reflection */
+                        xn = -xn;
+                        v1[0] = -v1[0];
+                    }
                 }
                 r->vx[s][i] = v1[0];
                 r->vy[s][i] = v1[1];
                 r->vz[s][i] = v1[2];
-                if (xn >= (double)cfg->nx) { /* absorbing wall */
+                if (left_out || xn >= (double)cfg->nx) { /* absorbing wall */
                     r->x[s][i] = -1.0;
                     absorbed[s] += 1;
                 } else {
@@ -810,8 +890,23 @@ void orc_step(orc_run* r, int32_t nsteps) {
             }
             r->absorbed_total[s] += absorbed[s];
         }
-        /* thermal source: ion-loss-balanced pairs */
-        if (cfg->nspecies == 2) {
+        if (cfg->geometry == ORC_GEOM_PLATES) {
+            /* flux injection through the plate at x = L, both species */
+            for (int s = 0; s < cfg->nspecies; ++s) {
+                r->acc_flux[s] += orc_wall_flux_per_step(cfg, s);
+                int64_t m = (int64_t)floor(r->acc_flux[s]);
+                r->acc_flux[s] -= (double)m;
+                ensure_capacity(r, s, r->n[s] + m);
+                for (int64_t k = 0; k < m; ++k) {
+                    double p[4];
+                    orc_wall_inject_particle(cfg, s, (uint32_t)k, (uint32_t)r->step, p);
+                    int64_t i = r->n[s] + k;
+                    r->x[s][i] = p[0]; r->vx[s][i] = p[1]; r->vy[s][i] = p[2]; r->vz[s][i] = p[3];
+                }
+                r->n[s] += m;
+                r->injected_total[s] += m;
+            }
+        } else if (cfg->nspecies == 2) { /* thermal source: ion-loss-balanced pairs */
             int64_t ni = absorbed[1];
             r->acc_e += (double)ni * (r->w[1] / r->w[0]);
             int64_t ne = (int64_t)floor(r->acc_e);
@@ -822,7 +917,7 @@ void orc_step(orc_run* r, int32_t nsteps) {
         deposit(r);
         solve_fields(r);
         r->step += 1;
-        orc_steady_feed(&r->steady, r->phi[0] - r->phi[cfg->nx], r->step);
+        orc_steady_feed(&r->steady, orc_monitor_potential(r), r->step);
         if (cfg->sort_every > 0 && r->step % cfg->sort_every == 0) orc_sort(r, NULL, NULL);
     }
 }

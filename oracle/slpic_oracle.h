@@ -30,7 +30,13 @@ extern "C" {
 
 enum { ORC_BETA_STEP = 0, ORC_BETA_SMOOTH = 1 };
 enum { ORC_KICK_EXACT = 0, ORC_KICK_MMP = 1 };
-enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2, ORC_PURPOSE_WARM_COUNT = 3, ORC_PURPOSE_WARM = 4 };
+enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2, ORC_PURPOSE_WARM_COUNT = 3, ORC_PURPOSE_WARM = 4,
+       ORC_PURPOSE_WALL = 5 };
+/* Geometry: the sheath (symmetry plane at x = 0, grounded absorbing wall at
+ * x = L, volume pair source) or the two conducting plates of Sec. IV
+ * (phi(0) = 0, phi(L) = bias, both absorbing, half-Maxwellian flux injected
+ * from the plate at x = L; the box starts empty). */
+enum { ORC_GEOM_SHEATH = 0, ORC_GEOM_PLATES = 1 };
 
 typedef struct {
     double charge, mass, temperature;
@@ -55,6 +61,9 @@ typedef struct {
     int32_t steady_window; /* steps per wall-potential window; 0: max(1, nx/4) */
     int32_t pad;
     double steady_tol;     /* relative spread of three window means; 0: 0.02 */
+    int32_t geometry;      /* ORC_GEOM_SHEATH / ORC_GEOM_PLATES               */
+    int32_t pad2;
+    double bias;           /* plates: phi(L) in T_e/e                         */
 } orc_config;
 
 /* Steady-state detector on the wall potential (a reading: the paper calls
@@ -99,6 +108,9 @@ void orc_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step
 
 /* --- grid ---------------------------------------------------------------- */
 void orc_poisson1d(int32_t nx, double dx, const double* Q, double* phi, double* E);
+void orc_poisson1d_plates(int32_t nx, double dx, const double* Q, double bias, double* phi, double* E);
+void orc_wall_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step, double out[4]);
+double orc_wall_flux_per_step(const orc_config* cfg, int s);
 
 /* --- run ----------------------------------------------------------------- */
 orc_run* orc_create(const orc_config* cfg);

@@ -96,6 +96,36 @@ def sheath2d(nx: int = 512, ny: int = 512, ppc: int = 64, u_over_vti: float = 3.
     return cfg
 
 
+PAPER_ION_MASS = 39.9 * 1836.0  # the paper's argon ion mass in electron masses
+
+
+def plates_sheath(v0_over_vte: float, ppc: int = 200, seed: int = 0, sort_every: int = 16,
+                  capacity_factor: float = 2.0, beta_kind: str = "step") -> dict:
+    """The paper's sheath experiment (Sec. IV), normalised to T_e = 2.2 eV,
+    n0 = 5e13 m^-3 (lambda_D = 0.156 cm, v_te = 6.2e5 m/s): conducting
+    plates 4 cm apart (25.65 lambda_D, 100 cells), phi(0) = 0, phi(L) = 12.5 V
+    = 5.68 T_e/e, electrons and argon ions (m = 39.9 * 1836 m_e, T_i = 0.5 eV)
+    injected through the plate at x = L as from a stationary plasma of density
+    n0, both plates absorbing, the box empty at the start.  v0 = v0_over_vte
+    * v_te with dt = dx/v0 (the paper: v0 = 9.8e3 m/s = 0.0158 v_te); v0 = inf
+    is PIC with dt = dx/(5 v_te).  ppc: g-particles per cell at density n0
+    (sets the weight)."""
+    L = 4.0 / 0.15595  # plate gap in Debye lengths
+    nx = 100
+    dx = L / nx
+    u = math.inf if math.isinf(v0_over_vte) else float(v0_over_vte)
+    dt = dx / 5.0 if math.isinf(u) else dx / u
+    ti = 0.5 / 2.2
+    return {
+        "nx": nx, "dx": dx, "dt": dt, "u": u, "beta_kind": beta_kind,
+        "species": [{"charge": -1.0, "mass": 1.0, "temperature": 1.0, "ppc": int(ppc)},
+                    {"charge": 1.0, "mass": PAPER_ION_MASS, "temperature": ti, "ppc": int(ppc)}],
+        "source_cells": 4, "seed": int(seed), "run": 0, "sort_every": int(sort_every), "sort_bucket": 1,
+        "capacity_factor": float(capacity_factor), "geometry": "plates", "bias": 12.5 / 2.2,
+        "steady_window": 0, "steady_tol": 0.0,
+    }
+
+
 def wave_test(v0_over_vphi: float, n: int = 100_000, seed: int = 0, cells: int = 100, periods_ramp: float = 20.0,
               phi_max: float = 0.1, beta_kind: str = "step"):
     """Test electrons in a prescribed traveling wave phi0(t) sin(k(x - v_phi t))
