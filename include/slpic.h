@@ -17,6 +17,15 @@
  * symmetry plane (specular particles, dphi/dx = 0), x = L a grounded
  * absorbing wall (phi = 0).  A thermal source injects electron/ion pairs in
  * the first source_cells cells, balancing the ion loss to the wall.
+ *
+ * Geometry SLPIC_GEOM_PLATES (the two-plate sheath of Sec. IV): conducting
+ * plates at x = 0 (phi = 0) and x = L (phi = bias), both absorbing; the box
+ * starts empty and both species enter through x = L with the one-sided flux
+ * of a stationary Maxwellian of unit density, n0 v_t / sqrt(2 pi) per unit
+ * area and time (the g-particles crossing carry the physical flux, Eq. 5):
+ * v_x = -v_t sqrt(-2 ln(1 - U)), v_y and v_z Maxwellian, placed a uniform
+ * fraction of the step's travel beta(|v|) |v_x| dt inside the plate (at most
+ * source_cells cells).  The monitored potential is phi at node nx/2.
  * Normalised units: x in electron Debye lengths, t in 1/omega_pe, v in the
  * electron thermal speed, phi in T_e/e, density in n0; e = m_e = eps0 = 1.
  *
@@ -65,6 +74,9 @@ enum { SLPIC_BETA_STEP = 0, SLPIC_BETA_SMOOTH = 1 };
  * FP32; SLPIC_F64: positions and velocities FP64. */
 enum { SLPIC_F32 = 0, SLPIC_F64 = 1 };
 
+/* Geometry of a run (slpic_run_config.geometry). */
+enum { SLPIC_GEOM_SHEATH = 0, SLPIC_GEOM_PLATES = 1 };
+
 /* Error flag bits reported in slpic_run_status.error_flags. */
 enum { SLPIC_FLAG_CAPACITY = 1, SLPIC_FLAG_NUMERIC = 2 };
 
@@ -98,6 +110,10 @@ typedef struct {
                            /* cell is loaded from the Maxwellian drifting at     */
                            /* V = Gamma/n (|V| <= 4 vt) with n dx <1/beta>/w     */
                            /* g-particles sampled as f/beta (Eq. 5)             */
+    int32_t geometry;      /* SLPIC_GEOM_SHEATH (0) or SLPIC_GEOM_PLATES; plates */
+                           /* need nx <= 16384 and no warm_profile               */
+    int32_t reserved;
+    double bias;           /* SLPIC_GEOM_PLATES: phi(L) in T_e/e; else unused   */
 } slpic_run_config;
 
 typedef struct {
@@ -123,6 +139,7 @@ typedef struct {
     int64_t injected_total[2]; /* particles injected by the source since load      */
     double acc_e;              /* fractional electron injection carried over       */
     double wall_potential;     /* phi(0) - phi(L) after the last field solve       */
+                               /* (plates: phi at node nx/2)                        */
     int32_t error_flags;       /* SLPIC_FLAG_* bits (sticky)                       */
     int32_t fixed_bits;        /* F32: fraction bits of the position fixed point   */
     double weight[2];          /* macroparticle weight per species, dx Z / ppc     */
@@ -130,6 +147,7 @@ typedef struct {
     int64_t windows;           /* closed wall-potential windows                    */
     double window_mean[3];     /* the last three window means of Phi_w, newest first */
     int64_t moment_samples;    /* samples in the moment window (slpic_moments_sample) */
+    double acc_flux[2];        /* plates: fractional wall injection per species     */
 } slpic_run_status;
 
 /* Bytes of device workspace needed for nruns runs (a sheath each) with the
@@ -194,6 +212,10 @@ int slpic_import_particles(void* ctx, int32_t run, int32_t species, const double
 /* Sync.  Sets the step counter (enters the source's Philox counter) and the
  * fractional electron-injection accumulator of one run. */
 int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e);
+
+/* Sync.  Sets the fractional wall-injection accumulators of one run of the
+ * plates geometry (h_acc: 2 doubles in [0, 1), electrons then ions). */
+int slpic_set_flux_counters(void* ctx, int32_t run, const double* h_acc);
 
 /* Recompute rho (Eq. A2c, from the stored particles) and the fields
  * (Eq. A2d) of every run without pushing.  Async. */

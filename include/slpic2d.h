@@ -73,7 +73,8 @@ typedef struct {
 } slpic2d_status;
 
 /* Bytes of device workspace for one 2D run with ny cells along y (a power of
- * two, 4..2048) and the given tuning (NULL = defaults).  run->nx, dx, dt, u,
+ * two, 4..2048) and the given tuning (NULL = defaults); run->geometry must be
+ * SLPIC_GEOM_SHEATH.  run->nx, dx, dt, u,
  * beta_kind, species, source_cells, seed, run_id and capacity_factor are
  * used as in slpic.h (ppc per cell of dx x dy; warm_profile must be NULL).
  * Returns 0 on an invalid configuration. */

@@ -141,6 +141,7 @@ def lib():
             "orc_nlive": (_I64, [_VP, _I32]),
             "orc_step_index": (_I64, [_VP]),
             "orc_acc_e": (_D, [_VP]),
+            "orc_acc_flux": (_D, [_VP, _I32]),
             "orc_absorbed_total": (_I64, [_VP, _I32]),
             "orc_injected_total": (_I64, [_VP, _I32]),
             "orc_get_particles": (None, [_VP, _I32, _PD, _PD, _PD, _PD]),
@@ -401,6 +402,10 @@ class Run:
     @property
     def acc_e(self) -> float:
         return lib().orc_acc_e(self._h)
+
+    def acc_flux(self) -> list:
+        """Plates: the fractional wall injection carried over, per species."""
+        return [lib().orc_acc_flux(self._h, s) for s in range(2)]
 
     def absorbed_total(self, s: int) -> int:
         return lib().orc_absorbed_total(self._h, s)

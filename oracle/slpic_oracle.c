@@ -991,6 +991,8 @@ void orc_set_counters(orc_run* r, int64_t step, double acc_e) {
     r->acc_e = acc_e;
 }
 
+double orc_acc_flux(const orc_run* r, int32_t s) { return r->acc_flux[s]; }
+
 void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E) {
     size_t nodes = (size_t)r->cfg.nx + 1;
     if (Q0) memcpy(Q0, r->Q[0], nodes * sizeof(double));

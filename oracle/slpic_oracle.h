@@ -140,6 +140,8 @@ void orc_get_particles(const orc_run* r, int32_t s, double* x, double* vx, doubl
 int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const double* vx,
                       const double* vy, const double* vz);
 void orc_set_counters(orc_run* r, int64_t step, double acc_e);
+/* Plates: the fractional wall injection carried over, per species. */
+double orc_acc_flux(const orc_run* r, int32_t s);
 void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E);
 void orc_get_steady(const orc_run* r, orc_steady* out);
 

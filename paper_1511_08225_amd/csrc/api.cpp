@@ -168,6 +168,10 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             c.source_cells < 1 || c.source_cells > c.nx ||
             (c.beta_kind != SLPIC_BETA_STEP && c.beta_kind != SLPIC_BETA_SMOOTH))
             return SLPIC_EINVAL;
+        const bool plates = c.geometry == SLPIC_GEOM_PLATES;
+        if ((c.geometry != SLPIC_GEOM_SHEATH && !plates) ||
+            (plates && (c.warm_profile || c.nx > kPlatesMaxCells || !std::isfinite(c.bias))))
+            return SLPIC_EINVAL;
         RunInfo& R = P.runs[r];
         R.nx = c.nx;
         R.nodes = c.nx + 1;
@@ -204,7 +208,9 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             } else {
                 step_mixture(R.ut[s], R.Ps[s], R.Pf[s]);
             }
-            R.nload[s] = (int64_t)c.nx * sp.ppc;
+            R.nload[s] = plates ? 0 : (int64_t)c.nx * sp.ppc;  // plates: the box starts empty
+            // plates: the one-sided flux v_t / sqrt(2 pi) of unit density, in g-particles per step
+            R.wall_flux[s] = plates ? R.vt[s] / std::sqrt(2.0 * M_PI) * c.dt / R.w[s] : 0.0;
             if (c.warm_profile) {
                 R.warm = 1;
                 const int64_t nw = plan_warm_species(R, c, r, s, P.warm_cells);
@@ -212,7 +218,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
                 R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), nw + 64);
                 R.nload[s] = nw;
             } else {
-                R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), R.nload[s] + 64);
+                const int64_t nref = (int64_t)c.nx * sp.ppc;  // slots sized on the load density
+                R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)nref), R.nload[s] + 64);
             }
             if (R.cap[s] > (int64_t(1) << 31) - 1) return SLPIC_EINVAL;
             R.poff[s] = poff;
@@ -222,6 +229,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             hoff += (int64_t)R.nkeys * R.ntiles[s];
         }
         R.inj_ratio = R.w[1] / R.w[0];
+        R.geom = plates ? kGeomPlates : kGeomSheath;
+        R.bias = plates ? c.bias : 0.0;
         if (c.steady_window < 0 || !(c.steady_tol >= 0.0)) return SLPIC_EINVAL;
         R.steady_window = c.steady_window > 0 ? c.steady_window : std::max(1, c.nx / 4);
         R.steady_tol = c.steady_tol > 0.0 ? c.steady_tol : 0.02;
@@ -687,6 +696,8 @@ int slpic_status_query(void* ctx, slpic_run_status* h_out, int32_t nruns) {
         o.windows = st[r].nwin;
         for (int k = 0; k < 3; ++k) o.window_mean[k] = st[r].win_mean[k];
         o.moment_samples = st[r].msamples;
+        o.acc_flux[0] = st[r].acc_w[0];
+        o.acc_flux[1] = st[r].acc_w[1];
     }
     return SLPIC_OK;
 }
@@ -790,6 +801,15 @@ int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e) {
     if (int rc = copy_h2d(&c->a.state[run].acc_e, &acc_e, sizeof acc_e)) return rc;
     c->steps_done = step;
     return SLPIC_OK;
+}
+
+int slpic_set_flux_counters(void* ctx, int32_t run, const double* h_acc) {
+    Context* c = ctx_of(ctx);
+    if (!c || !h_acc || run < 0 || run >= c->P.nruns || c->P.runs[run].geom != kGeomPlates) return SLPIC_EINVAL;
+    for (int s = 0; s < 2; ++s)
+        if (!(h_acc[s] >= 0.0 && h_acc[s] < 1.0)) return SLPIC_EINVAL;
+    HIP_TRY(hipDeviceSynchronize());
+    return copy_h2d(&c->a.state[run].acc_w[0], h_acc, 2 * sizeof(double));
 }
 
 int slpic_refresh_fields(void* ctx, void* stream) {

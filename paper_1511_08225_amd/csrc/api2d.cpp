@@ -49,7 +49,7 @@ int clog2(int64_t v) {
 }
 
 int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Plan2& P) {
-    if (!c) return SLPIC_EINVAL;
+    if (!c || c->geometry != SLPIC_GEOM_SHEATH) return SLPIC_EINVAL;  // the plates geometry is 1D only
     slpic2d_tuning t{};
     if (tin) t = *tin;
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;

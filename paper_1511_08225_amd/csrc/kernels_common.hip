@@ -35,6 +35,8 @@ __global__ void k_init_state(KArgs a, int nruns) {
     st->nwin = 0;
     st->steady_step = -1;
     st->msamples = 0;
+    st->acc_w[0] = 0.0;
+    st->acc_w[1] = 0.0;
 }
 
 __global__ __launch_bounds__(kFieldThreads) void k_field(KArgs a, int advance) {

@@ -12,6 +12,10 @@ constexpr int kPurposeLoad = 1;
 constexpr int kPurposeInject = 2;
 constexpr int kPurposeWarmCount = 3;  // warm load: rounding of a cell's count
 constexpr int kPurposeWarm = 4;       // warm load: one particle
+constexpr int kPurposeWall = 5;       // plates: a particle entering through x = L
+constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
+constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
+constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
 constexpr int kCountSlots = 64;    // spread slots of the per-step particle counters
 
@@ -40,8 +44,10 @@ struct RunInfo {
     int32_t steady_window;       // steps per wall-potential window
     int32_t warm;                // 1: loaded from predicted profiles (k_load_warm), not cold
     int32_t retire;              // 1: frozen once steady (steady_step >= 0)
-    int32_t pad_r;
+    int32_t geom;                // kGeomSheath / kGeomPlates
     double steady_tol;           // relative spread of three window means that counts as steady
+    double bias;                 // plates: phi(L)
+    double wall_flux[kMaxSpecies];  // plates: g-particles entering per step, per species
 };
 
 // Mutable per-run state, updated on the device.
@@ -61,6 +67,7 @@ struct alignas(64) RunState {
     int64_t nwin;                // closed windows
     int64_t steady_step;         // step count when first steady, -1 before
     int64_t msamples;            // moment samples in the window accumulator
+    double acc_w[kMaxSpecies];   // plates: fractional wall injection carried over
 };
 
 // A run frozen under retire_steady: once its steady detector has flagged it,

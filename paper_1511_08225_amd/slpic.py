@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslpic.so")
 
 SLPIC_F32, SLPIC_F64 = 0, 1
+GEOM_SHEATH, GEOM_PLATES = 0, 1
 BETA_STEP, BETA_SMOOTH = 0, 1
 FLAG_CAPACITY, FLAG_NUMERIC = 1, 2
 PROFILE_CLASSES = ("push", "inject", "field", "sort")
@@ -39,7 +40,8 @@ class RunConfig(ctypes.Structure):
                 ("nspecies", ctypes.c_int32), ("source_cells", ctypes.c_int32),
                 ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run_id", ctypes.c_int32),
                 ("steady_window", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
-                ("steady_tol", ctypes.c_double), ("warm_profile", ctypes.c_void_p)]
+                ("steady_tol", ctypes.c_double), ("warm_profile", ctypes.c_void_p),
+                ("geometry", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bias", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -56,7 +58,8 @@ class RunStatus(ctypes.Structure):
                 ("wall_potential", ctypes.c_double), ("error_flags", ctypes.c_int32),
                 ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2),
                 ("steady_step", ctypes.c_int64), ("windows", ctypes.c_int64),
-                ("window_mean", ctypes.c_double * 3), ("moment_samples", ctypes.c_int64)]
+                ("window_mean", ctypes.c_double * 3), ("moment_samples", ctypes.c_int64),
+                ("acc_flux", ctypes.c_double * 2)]
 
     def as_dict(self) -> dict:
         return {"step": self.step, "nslots": list(self.nslots), "capacity": list(self.capacity),
@@ -65,7 +68,8 @@ class RunStatus(ctypes.Structure):
                 "wall_potential": self.wall_potential, "error_flags": self.error_flags,
                 "fixed_bits": self.fixed_bits, "weight": list(self.weight),
                 "steady_step": self.steady_step, "windows": self.windows,
-                "window_mean": list(self.window_mean), "moment_samples": self.moment_samples}
+                "window_mean": list(self.window_mean), "moment_samples": self.moment_samples,
+                "acc_flux": list(self.acc_flux)}
 
 
 class WaveConfig(ctypes.Structure):
@@ -131,6 +135,7 @@ def lib():
             "slpic_export_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, _PI64]),
             "slpic_import_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, i64]),
             "slpic_set_counters": (ctypes.c_int, [_P, i32, i64, ctypes.c_double]),
+            "slpic_set_flux_counters": (ctypes.c_int, [_P, i32, _PD]),
             "slpic_refresh_fields": (ctypes.c_int, [_P, _P]),
             "slpic_export_grid": (ctypes.c_int, [_P, i32, _PD, _PD, _PD]),
             "slpic_sort_now": (ctypes.c_int, [_P, _P]),
@@ -179,8 +184,9 @@ def _beta_kind(v) -> int:
 
 
 def run_config(cfg: dict) -> RunConfig:
-    """Marshal a sheath description (nx, dx, dt, u, beta_kind, species,
-    source_cells, seed, run, capacity_factor) into the C struct."""
+    """Marshal a run description (nx, dx, dt, u, beta_kind, species,
+    source_cells, seed, run, capacity_factor, geometry, bias) into the C
+    struct."""
     c = RunConfig()
     c.nx = int(cfg["nx"])
     c.beta_kind = _beta_kind(cfg.get("beta_kind", "step"))
@@ -198,6 +204,9 @@ def run_config(cfg: dict) -> RunConfig:
     c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
     c.steady_window = int(cfg.get("steady_window", 0))
     c.steady_tol = float(cfg.get("steady_tol", 0.0))
+    geom = cfg.get("geometry", "sheath")
+    c.geometry = {"sheath": GEOM_SHEATH, "plates": GEOM_PLATES}[geom] if isinstance(geom, str) else int(geom)
+    c.bias = float(cfg.get("bias", 0.0))
     return c
 
 
@@ -321,6 +330,10 @@ class Sim:
 
     def set_counters(self, run: int, step: int, acc_e: float):
         _check(lib().slpic_set_counters(self._ctx, run, int(step), float(acc_e)), "slpic_set_counters")
+
+    def set_flux_counters(self, run: int, acc):
+        a = np.ascontiguousarray(acc, dtype=np.float64)
+        _check(lib().slpic_set_flux_counters(self._ctx, run, _dp(a)), "slpic_set_flux_counters")
 
     def grid(self, run: int = 0):
         nodes = self.configs[run]["nx"] + 1

@@ -39,6 +39,8 @@ def push_oracle_to_gpu(sim, r: int, run: "oracle.Run", quantize: bool):
             set_oracle_particles(run, s, x, vx, vp2)
         sim.import_particles(r, s, x, vx, vp2)
     sim.set_counters(r, run.step_index, run.acc_e)
+    if run.cfg.get("geometry") == "plates":
+        sim.set_flux_counters(r, run.acc_flux())
     run.refresh_fields()
     sim.refresh_fields()
 

@@ -111,3 +111,31 @@ def test_2d_workspace_planning_validates_configs():
     t64 = slpic.Tuning2D()
     t64.precision = slpic.SLPIC_F64
     assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(t64)) > n
+
+
+def test_plates_planning_validates_configs():
+    """The plates geometry plans like a sheath run sized on the load density
+    (its box starts empty); it rejects warm profiles, more than 16384 cells,
+    a non-finite bias, an unknown geometry and the 2D library."""
+    import torch  # noqa: F401
+    import numpy as np
+    import workloads
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    t = slpic.tuning(precision="f64", sort_every=1)
+    cfg = workloads.plates_sheath(0.0158, ppc=40)
+    good = slpic.run_config(cfg)
+    assert good.geometry == slpic.GEOM_PLATES and good.bias == cfg["bias"]
+    n_pl = L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(t))
+    sh = slpic.run_config(dict(cfg, geometry="sheath"))
+    assert n_pl > 0 and n_pl == L.slpic_workspace_bytes(ctypes.byref(sh), 1, ctypes.byref(t))
+    prof = np.zeros((5, 256))
+    bad = slpic.run_config(cfg)
+    bad.warm_profile = prof.ctypes.data
+    assert L.slpic_workspace_bytes(ctypes.byref(bad), 1, ctypes.byref(t)) == 0
+    for field, val in (("geometry", 2), ("bias", float("nan")), ("nx", 16385)):
+        bad = slpic.run_config(cfg)
+        setattr(bad, field, val)
+        assert L.slpic_workspace_bytes(ctypes.byref(bad), 1, ctypes.byref(t)) == 0, field
+    assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(slpic.Tuning2D())) == 0
+    assert "slpic_set_flux_counters" in _declared_functions()
