@@ -475,6 +475,105 @@ def run_wave(args, n: int = 4_194_304, steps: int = 4000, per_launch: int = 500)
     return out
 
 
+def _plates_leg(v0, ppc, runs, t_us, avg_us, graph_steps=16, samples=200):
+    """One side of the plates experiment: `runs` seeds of the plates workload
+    at speed limit v0 (inf = PIC) in one FP32 context on a side stream (so
+    that blocks of graph_steps steps replay as HIP graphs), stepped from the
+    empty box to t_us microseconds, with the moments sampled over the last
+    avg_us at a stride of whole graph blocks.  Returns the wall time (host
+    clock around the synchronised run), the steps, the final status of run 0
+    and the run-averaged window means (phi, n_e, n_i)."""
+    import torch
+    import numpy as np
+    import workloads
+    from paper_1511_08225_amd import slpic
+    cfg = workloads.plates_sheath(v0, ppc=ppc, sort_every=16, capacity_factor=0.5)
+    cfg["steady_window"] = max(1, workloads.plates_steps(cfg, 1.0))  # windows of 1 us of simulated time
+    total = workloads.plates_steps(cfg, t_us)
+    avg = workloads.plates_steps(cfg, avg_us)
+    stride = max(1, avg // samples)
+    if stride >= graph_steps:
+        stride = stride // graph_steps * graph_steps
+    in_step = graph_steps % stride == 0  # sampled inside the captured step blocks
+    nsamp = avg // stride
+    configs = [dict(cfg, seed=1000 + r, run=r) for r in range(runs)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        # 256-slot push chunks and 2048-slot sort tiles: a few 1e5 particles
+        # spread over more wavefronts and sort workgroups than the defaults give
+        sim = slpic.Sim(configs, precision="f32", sort_every=16, graph_steps=graph_steps, chunk=256,
+                        sort_tile=2048)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        first = total - nsamp * stride
+        sim.step(first)
+        if in_step:
+            sim.set_sampling(stride)
+            sim.step(nsamp * stride)
+        else:
+            for _ in range(nsamp):
+                sim.step(stride)
+                sim.moments_sample(-1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = sim.status()
+        win = np.mean([sim.moments_window(r).cpu().numpy() for r in range(runs)], axis=0)
+        pushed = sim.pushed_total()
+        sim.close()
+    flags = [s["error_flags"] for s in st]
+    if any(flags):
+        raise RuntimeError(f"plates run raised error flags {flags}")
+    steady = [s["steady_step"] for s in st]
+    return {"v0_over_vte": v0, "dt": cfg["dt"], "steps": total, "wall_s": wall, "ms_per_step": wall * 1e3 / total,
+            "pushes_per_s": pushed / wall, "samples": nsamp, "sample_stride": stride,
+            "final_particles": [st[0]["nslots"][0], st[0]["nslots"][1]],
+            "steady_us": [None if k < 0 else k * cfg["dt"] / workloads.PAPER_OMEGA_PE_US for k in steady],
+            "profiles": {"phi": win[0], "n_e": win[1], "n_i": win[4]}}
+
+
+def run_plates(args, ppc: int = 9000, runs: int = 1) -> dict:
+    """The paper's sheath experiment (Sec. IV): PIC (dt = dx/(5 v_te)) and
+    SLPIC (v0 = 0.0158 v_te, dt = dx/v0) from the empty box to 24 us, the
+    time-averaged phi, n_e, n_i over the last 8 us (one ion crossing) of
+    each, their agreement (relative L2 over the interior nodes), and the
+    wall-time ratio; the oracle's SLPIC run beside it on a bounded sample."""
+    import numpy as np
+    import workloads
+    P = workloads.PLATES_PAPER
+    sl = _plates_leg(0.0158, ppc, runs, P["t_steady_us"], P["t_cross_us"])
+    pic = _plates_leg(math.inf, ppc, runs, P["t_steady_us"], P["t_cross_us"])
+    agree = {}
+    for k in ("phi", "n_e", "n_i"):
+        a, b = sl["profiles"][k][1:-1], pic["profiles"][k][1:-1]
+        agree[k + "_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    prof = {k: {"slpic": [round(float(v), 4) for v in sl["profiles"][k][::10]],
+                "pic": [round(float(v), 4) for v in pic["profiles"][k][::10]]} for k in ("phi", "n_e", "n_i")}
+    for leg in (sl, pic):
+        del leg["profiles"]
+    out = {"metric": "wall-time speed-up of SLPIC over PIC to the steady two-plate sheath",
+           "value": pic["wall_s"] / sl["wall_s"], "unit": "x", "higher_is_better": True, "dtype": "f32",
+           "config": {"workload": (f"two-plate argon sheath of Sec. IV: 100 cells over 25.65 Debye lengths, bias "
+                                   f"5.68 T_e/e, both species injected through x = L, {ppc} g-particles per cell "
+                                   f"at n0, {runs} run(s) per context, 24 us simulated, profiles averaged over "
+                                   f"the last 8 us")},
+           "slpic": sl, "pic": pic, "step_ratio": pic["steps"] / sl["steps"], "agreement": agree,
+           "profiles_every_10_nodes": prof,
+           "paper": {"speedup": P["speedup"], "pic_steps": P["pic_steps"], "slpic_steps": P["slpic_steps"],
+                     "ions": P["ions"], "electrons": P["electrons"]}}
+    if not args.no_cpu_baseline:
+        import oracle
+        cfg = workloads.plates_sheath(0.0158, ppc=ppc // 10, sort_every=16, capacity_factor=0.5)
+        run = oracle.Run(cfg)
+        n = workloads.plates_steps(cfg, P["t_steady_us"])
+        t0 = time.perf_counter()
+        run.step(n)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": dt * 10, "unit": "s to 24 us (SLPIC)", "cores": 1, "kind": "oracle",
+                               "sample": f"the SLPIC run at {ppc // 10} g-particles per cell (a tenth of the "
+                                         f"particles), all {n} steps, FP64 C oracle, one thread; its time x 10"}
+    return out
+
+
 def launch_params(cfg, args) -> dict:
     """Push chunk, workgroup size, sort period and bucket: from the autotuner
     (cached per workload signature) unless given on the command line."""
@@ -535,6 +634,10 @@ def main() -> int:
     ap.add_argument("--no-2d", action="store_true", help="leave out the 2D3V sheath measurement")
     ap.add_argument("--only-wave", action="store_true", help="the wave-particle test-particle line alone, and exit")
     ap.add_argument("--no-wave", action="store_true", help="leave out the wave-particle measurement")
+    ap.add_argument("--only-plates", action="store_true", help="the two-plate PIC vs SLPIC experiment alone, and exit")
+    ap.add_argument("--no-plates", action="store_true", help="leave out the two-plate PIC vs SLPIC experiment")
+    ap.add_argument("--plates-ppc", type=int, default=9000, help="g-particles per cell at n0 in the plates experiment")
+    ap.add_argument("--plates-runs", type=int, default=1, help="seeds per context in the plates experiment")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the counter workload (copy calibration + direct-launch steps) and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -564,6 +667,9 @@ def main() -> int:
         return 0
     if args.only_wave:
         print(json.dumps(run_wave(args)), flush=True)
+        return 0
+    if args.only_plates:
+        print(json.dumps(run_plates(args, args.plates_ppc, args.plates_runs)), flush=True)
         return 0
 
     import workloads
@@ -630,6 +736,8 @@ def main() -> int:
         line["sheath_2d"] = run_2d(args)
     if not args.no_wave:
         line["wave_test"] = run_wave(args)
+    if not args.no_plates:
+        line["plates_sheath"] = run_plates(args, args.plates_ppc, args.plates_runs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

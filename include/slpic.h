@@ -182,6 +182,14 @@ int slpic_moments(void* ctx, int32_t run, double* d_out, void* stream);
  * between slpic_step calls at the cadence wanted). */
 int slpic_moments_sample(void* ctx, int32_t run, void* stream);
 
+/* In-step sampling: from the next step on, every step whose count (the
+ * context's step counter, as in slpic_step) is a multiple of `every` ends
+ * with slpic_moments_sample(ctx, -1), inside the captured HIP graphs too, so
+ * that time averages cost no host round trip; 0 turns it off.  With
+ * tuning.graph_steps > 0, `every` must divide graph_steps (SLPIC_EINVAL
+ * otherwise); the captured graph is rebuilt at the next replay.  Sync. */
+int slpic_set_sampling(void* ctx, int32_t every);
+
 /* The window mean of one run's moment samples, in the layout of
  * slpic_moments (all zero without samples), to the caller's device buffer;
  * reset != 0 then empties the window.  Async on stream. */

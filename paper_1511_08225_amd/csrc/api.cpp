@@ -124,7 +124,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
-        totals, counts, push_err, Macc, btot, history, total;
+        totals, counts, push_err, Macc, btot, history, injb, total;
 };
 
 struct Plan {
@@ -135,6 +135,7 @@ struct Plan {
     std::vector<int> run_chunk0, run_nchunks;
     std::vector<Tile> tiles;
     std::vector<WarmCell> warm_cells;
+    std::vector<int4> injb;  // plates: wall-injection workgroups (run, species, first particle, 0)
     int64_t total_slots = 0, total_nodes = 0, hist_entries = 0;
     int max_nodes = 0, max_src = 0, max_nkeys = 0;
     Layout L{};
@@ -170,7 +171,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             return SLPIC_EINVAL;
         const bool plates = c.geometry == SLPIC_GEOM_PLATES;
         if ((c.geometry != SLPIC_GEOM_SHEATH && !plates) ||
-            (plates && (c.warm_profile || c.nx > kPlatesMaxCells || !std::isfinite(c.bias))))
+            (plates && (c.warm_profile || c.nx > kPlatesMaxCells || c.source_cells > kPlatesMaxSource ||
+                        !std::isfinite(c.bias))))
             return SLPIC_EINVAL;
         RunInfo& R = P.runs[r];
         R.nx = c.nx;
@@ -262,6 +264,18 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         }
         P.run_nchunks[r] = (int)P.chunks.size() - P.run_chunk0[r];
     }
+    // plates: the wall injection of a step (at most floor(wall_flux) + 1
+    // particles per species) runs in extra workgroups of the push launch
+    for (int r = 0; r < nruns; ++r) {
+        const RunInfo& R = P.runs[r];
+        if (R.geom != kGeomPlates) continue;
+        for (int s = 0; s < 2; ++s) {
+            const double most = std::floor(R.wall_flux[s]) + 1.0;
+            if (!(most < 1e9)) return SLPIC_EINVAL;
+            for (int64_t k = 0; k < (int64_t)most; k += t.block) P.injb.push_back(int4{r, s, (int)k, 0});
+        }
+    }
+    if (P.injb.size() > (size_t)1 << 20) return SLPIC_EINVAL;
     const size_t psz = t.precision == SLPIC_F32 ? 4 : 8;  // int32 fixed point or double
     const size_t vsz = t.precision == SLPIC_F32 ? 4 : 8;
     Layout& L = P.L;
@@ -294,6 +308,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.Macc = take(sizeof(double) * 7 * P.total_nodes);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
+    L.injb = take(sizeof(int4) * P.injb.size());
     L.total = o;
     return SLPIC_OK;
 }
@@ -327,6 +342,7 @@ struct Context {
     size_t pg_used = 0;
     ProfGraph* capturing = nullptr;  // events recorded during a capture go here
     bool pgraph_failed = false;
+    int sample_every = 0;  // in-step moment sampling period (0: off)
     ~Context() {
         if (gexec) hipGraphExecDestroy(gexec);
         for (auto& v : ev)
@@ -411,6 +427,15 @@ int do_sort(Context* c, hipStream_t s) {
 }
 
 // One leapfrog step of every run; `local_step` decides the sort.
+// The moments of every run added to their device windows (slpic_moments_sample).
+void sample_all(Context* c, hipStream_t s) {
+    if (prec(c) == SLPIC_F32)
+        launch_moments_f32(c->a, 0, (int)c->P.chunks.size(), 256, c->moments_lds, c->a.Macc, 1, s);
+    else
+        launch_moments_f64(c->a, 0, (int)c->P.chunks.size(), 256, c->moments_lds, c->a.Macc, 1, s);
+    launch_moments_sample_finish(c->a, 0, c->P.nruns, s);
+}
+
 int one_step(Context* c, int64_t local_step, hipStream_t s) {
     int rc;
     if ((rc = timed(c, 0, s, [&] { l_push(c, true, s); }))) return rc;
@@ -418,6 +443,7 @@ int one_step(Context* c, int64_t local_step, hipStream_t s) {
     const int se = c->P.tun.sort_every;
     if (se > 0 && (local_step + 1) % se == 0)
         if ((rc = do_sort(c, s))) return rc;
+    if (c->sample_every > 0 && (local_step + 1) % c->sample_every == 0) sample_all(c, s);
     return SLPIC_OK;
 }
 
@@ -541,6 +567,8 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.push_err = (int*)(w + L.push_err);
     a.Macc = (double*)(w + L.Macc);
     a.history = (double*)(w + L.history);
+    a.injb = (const int4*)(w + L.injb);
+    a.ninjb = (int32_t)c->P.injb.size();
     c->btot = (long long*)(w + L.btot);
     const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
     c->push_lds = (size_t)c->P.max_nodes * (8 + tsz) + 16;
@@ -566,6 +594,9 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     INIT_TRY(hipMemcpyAsync((void*)a.tiles, c->P.tiles.data(), sizeof(Tile) * c->P.tiles.size(),
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
+    if (!c->P.injb.empty())
+        INIT_TRY(hipMemcpyAsync((void*)a.injb, c->P.injb.data(), sizeof(int4) * c->P.injb.size(),
+                                hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     launch_init_state(a, nruns, s);
     launch_zero(a.Qacc, 2 * c->P.total_nodes, s);
     launch_zero(a.Macc, 7 * c->P.total_nodes, s);
@@ -607,7 +638,8 @@ int slpic_step(void* ctx, int32_t nsteps, void* stream) {
     int32_t done = 0;
     while (done < nsteps) {
         const int gl = c->P.tun.graph_steps;
-        if (graphs && nsteps - done >= gl && (se == 0 || c->steps_done % se == 0)) {
+        if (graphs && nsteps - done >= gl && (se == 0 || c->steps_done % se == 0) &&
+            (c->sample_every == 0 || c->steps_done % c->sample_every == 0)) {
             hipGraphExec_t ex = nullptr;
             if (c->prof) {
                 ProfGraph* pg = next_prof_graph(c, s);
@@ -859,21 +891,40 @@ int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, 
     return SLPIC_OK;
 }
 
+static void drop_prof_graphs(Context* c) {
+    for (auto& g : c->pgraphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        for (auto& v : g.ev)
+            for (auto& e : v) {
+                if (e.a) hipEventDestroy(e.a);
+                if (e.b) hipEventDestroy(e.b);
+            }
+    }
+    c->pgraphs.clear();
+    c->pg_used = 0;
+}
+
+int slpic_set_sampling(void* ctx, int32_t every) {
+    Context* c = ctx_of(ctx);
+    if (!c || every < 0) return SLPIC_EINVAL;
+    const int gl = c->P.tun.graph_steps;
+    if (every > 0 && gl > 0 && gl % every) return SLPIC_EINVAL;
+    if (every == c->sample_every) return SLPIC_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    if (c->gexec) {  // captured with the old step sequence
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    drop_prof_graphs(c);
+    c->sample_every = every;
+    return SLPIC_OK;
+}
+
 int slpic_profile(void* ctx, int32_t enable) {
     Context* c = ctx_of(ctx);
     if (!c) return SLPIC_EINVAL;
     HIP_TRY(hipDeviceSynchronize());
-    if (c->prof_mask != (enable & 15)) {  // captured profiling graphs hold the old event layout
-        for (auto& g : c->pgraphs) {
-            if (g.exec) hipGraphExecDestroy(g.exec);
-            for (auto& v : g.ev)
-                for (auto& e : v) {
-                    if (e.a) hipEventDestroy(e.a);
-                    if (e.b) hipEventDestroy(e.b);
-                }
-        }
-        c->pgraphs.clear();
-    }
+    if (c->prof_mask != (enable & 15)) drop_prof_graphs(c);  // they hold the old event layout
     c->prof = (enable & 15) != 0;
     c->prof_mask = enable & 15;
     for (auto& u : c->ev_used) u = 0;

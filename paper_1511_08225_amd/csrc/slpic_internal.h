@@ -16,6 +16,7 @@ constexpr int kPurposeWall = 5;       // plates: a particle entering through x =
 constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
 constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
 constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers
+constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the push LDS window
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
 constexpr int kCountSlots = 64;    // spread slots of the per-step particle counters
 
@@ -127,6 +128,8 @@ struct KArgs {
     int* push_err;        // [run]: error flags raised by the last push
     int32_t* perm;        // last sort's permutation (new slot -> old slot)
     double* Macc;         // moment window accumulators [run]: 7 rows of nodes at 7*goff
+    const int4* injb;     // plates: wall-injection workgroups of the push launch (run, species, first, 0)
+    int32_t ninjb;        // their count (0 without plates runs)
 };
 
 }  // namespace slpic

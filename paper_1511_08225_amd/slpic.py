@@ -136,6 +136,7 @@ def lib():
             "slpic_import_particles": (ctypes.c_int, [_P, i32, i32, _PD, _PD, _PD, i64]),
             "slpic_set_counters": (ctypes.c_int, [_P, i32, i64, ctypes.c_double]),
             "slpic_set_flux_counters": (ctypes.c_int, [_P, i32, _PD]),
+            "slpic_set_sampling": (ctypes.c_int, [_P, i32]),
             "slpic_refresh_fields": (ctypes.c_int, [_P, _P]),
             "slpic_export_grid": (ctypes.c_int, [_P, i32, _PD, _PD, _PD]),
             "slpic_sort_now": (ctypes.c_int, [_P, _P]),
@@ -362,6 +363,11 @@ class Sim:
         """Add the current moments of one run (or all, run = -1) to the
         device moment windows."""
         _check(lib().slpic_moments_sample(self._ctx, int(run), self._stream()), "slpic_moments_sample")
+
+    def set_sampling(self, every: int):
+        """Sample the moments of every run inside the step sequence (graphs
+        included) at each step count that is a multiple of `every`; 0 = off."""
+        _check(lib().slpic_set_sampling(self._ctx, int(every)), "slpic_set_sampling")
 
     def moments_window(self, run: int = 0, reset: bool = False) -> torch.Tensor:
         """Window mean of the sampled moments of one run (layout of moments())."""

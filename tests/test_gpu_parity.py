@@ -322,17 +322,63 @@ def test_batched_runs_match_their_oracles(gpu_lib):
             assert rel_inf(mg[row], mo[row]) <= 1e-11, (r, row)
 
 
-def test_graph_replay_matches_direct_launches(gpu_lib):
-    cfg = workloads.small_sheath(seed=8)
-    a = gpu_lib.Sim(cfg, precision="f64", sort_every=4, graph_steps=8)
-    b = gpu_lib.Sim(cfg, precision="f64", sort_every=4, graph_steps=0)
-    for _ in range(3):
+@pytest.mark.parametrize("cfg_name", ["sheath", "plates"])
+def test_graph_replay_matches_direct_launches(gpu_lib, cfg_name):
+    """Blocks of 8 steps captured once and replayed as a HIP graph (on a side
+    stream: the library captures only on a non-default stream) against the
+    same steps launched directly, checked after every replay with host
+    reads and synchronisations between the replays."""
+    import torch
+    cfg = (workloads.small_sheath(seed=8) if cfg_name == "sheath"
+           else workloads.plates_sheath(0.0158, ppc=200, seed=8))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = gpu_lib.Sim(cfg, precision="f64", sort_every=4, graph_steps=8)
+        b = gpu_lib.Sim(cfg, precision="f64", sort_every=4, graph_steps=0)
+        for k in range(4):
+            print_case(f"graph replay {cfg_name} block {k}")
+            a.step(8)
+            b.step(8)
+            ga, gb = a.grid(0), b.grid(0)
+            for s in range(2):
+                if np.abs(gb["Q"][s]).max() > 0:
+                    assert rel_inf(ga["Q"][s], gb["Q"][s]) <= 1e-9, (k, s)
+            sa, sb = a.status(0), b.status(0)
+            assert sa["nslots"] == sb["nslots"] and sa["injected_total"] == sb["injected_total"], k
+        assert a.status(0)["step"] == b.status(0)["step"] == 32
+        a.close()
+        b.close()
+
+
+def test_in_step_sampling_matches_host_sampling(gpu_lib):
+    """Moments sampled inside the step sequence (graph blocks of 8 steps
+    replayed on a side stream, a sample every 2nd step) against the same
+    samples taken from the host after direct-launched steps."""
+    import torch
+    cfg = workloads.plates_sheath(0.0158, ppc=200, seed=9)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = gpu_lib.Sim(cfg, precision="f64", sort_every=4, graph_steps=8)
+        b = gpu_lib.Sim(cfg, precision="f64", sort_every=4, graph_steps=0)
+        with pytest.raises(gpu_lib.SlpicError):
+            a.set_sampling(3)  # must divide the graph block
+        a.step(5)  # the graph blocks start once the step count is aligned again
+        b.step(5)
+        a.set_sampling(2)
+        a.step(35)
+        for k in range(6, 41):
+            b.step(1)
+            if k % 2 == 0:
+                b.moments_sample(-1)
+        print_case("in-step sampling window")
+        wa, wb = a.moments_window(0).cpu().numpy(), b.moments_window(0).cpu().numpy()
+        assert a.status(0)["moment_samples"] == b.status(0)["moment_samples"] == 18
+        assert np.abs(wa - wb).max() <= 1e-9 * np.abs(wb).max()
+        a.set_sampling(0)
         a.step(8)
-        b.step(8)
-        ga, gb = a.grid(0), b.grid(0)
-        for s in range(2):
-            assert rel_inf(ga["Q"][s], gb["Q"][s]) <= 1e-9
-    assert a.status(0)["step"] == b.status(0)["step"] == 24
+        assert a.status(0)["moment_samples"] == 18
+        a.close()
+        b.close()
 
 
 def test_capacity_overflow_sets_sticky_flag(gpu_lib):

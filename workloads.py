@@ -97,6 +97,12 @@ def sheath2d(nx: int = 512, ny: int = 512, ppc: int = 64, u_over_vti: float = 3.
 
 
 PAPER_ION_MASS = 39.9 * 1836.0  # the paper's argon ion mass in electron masses
+# 1 microsecond in 1/omega_pe at the paper's n0 = 5e13 m^-3 (omega_pe = 3.989e8 /s)
+PAPER_OMEGA_PE_US = 398.9
+PLATES_PAPER = {  # what the paper reports for its sheath experiment (Sec. IV)
+    "t_steady_us": 24.0, "t_cross_us": 8.0, "pic_steps": 1.9e5, "slpic_steps": 600,
+    "speedup": 160.0, "ions": 8.3e4, "electrons": 1.1e5,
+}
 
 
 def plates_sheath(v0_over_vte: float, ppc: int = 200, seed: int = 0, sort_every: int = 16,
@@ -124,6 +130,11 @@ def plates_sheath(v0_over_vte: float, ppc: int = 200, seed: int = 0, sort_every:
         "capacity_factor": float(capacity_factor), "geometry": "plates", "bias": 12.5 / 2.2,
         "steady_window": 0, "steady_tol": 0.0,
     }
+
+
+def plates_steps(cfg: dict, t_us: float) -> int:
+    """Steps of the plates workload cfg covering t_us microseconds."""
+    return int(round(t_us * PAPER_OMEGA_PE_US / cfg["dt"]))
 
 
 def wave_test(v0_over_vphi: float, n: int = 100_000, seed: int = 0, cells: int = 100, periods_ramp: float = 20.0,
