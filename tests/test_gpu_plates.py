@@ -193,3 +193,61 @@ def test_flux_counters_argument_checks(gpu_lib):
     sim.set_flux_counters(0, [0.25, 0.75])
     assert sim.status(0)["acc_flux"] == [0.25, 0.75]
     sim.close()
+
+
+def _to_24us(gpu_lib, v0, ppc, runs):
+    """Runs of the plates workload from the empty box to 24 us, FP32, with
+    the moments averaged over the last 8 us; returns the run-mean profiles
+    (phi, n_e, n_i), the step count and the final status of run 0."""
+    import torch
+    cfg = workloads.plates_sheath(v0, ppc=ppc, sort_every=16, capacity_factor=0.5)
+    total = workloads.plates_steps(cfg, 24.0)
+    avg = workloads.plates_steps(cfg, 8.0)
+    stride = 1 if avg < 400 else avg // 200 // 16 * 16
+    nsamp = avg // stride
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sim = gpu_lib.Sim([dict(cfg, seed=500 + r, run=r) for r in range(runs)], precision="f32", sort_every=16,
+                          graph_steps=16, chunk=256, sort_tile=2048)
+        sim.step(total - nsamp * stride)
+        if stride == 1:
+            sim.set_sampling(1)
+            sim.step(nsamp)
+        else:
+            for _ in range(nsamp):
+                sim.step(stride)
+                sim.moments_sample(-1)
+        win = np.mean([sim.moments_window(r).cpu().numpy() for r in range(runs)], axis=0)
+        st = sim.status()
+        sim.close()
+    assert all(s["error_flags"] == 0 for s in st)
+    assert all(s["moment_samples"] == nsamp for s in st)
+    return win[[0, 1, 4]], total, st[0]
+
+
+def test_slpic_reaches_the_pic_steady_state(gpu_lib):
+    """The paper's sheath experiment at reduced particle count (2000
+    g-particles per cell at n0, two seeds per side): after 24 us from the
+    empty box, SLPIC at v0 = 0.0158 v_te (590 steps) and PIC (186625 steps)
+    give the same time-averaged potential and densities within noise, and
+    the particle counts of both sides settle near each other."""
+    sl, n_sl, st_sl = _to_24us(gpu_lib, 0.0158, 2000, 2)
+    print_case("plates physics: PIC leg")
+    pic, n_pic, st_pic = _to_24us(gpu_lib, math.inf, 2000, 2)
+    assert n_sl == 590 and n_pic == 186625
+    names = ("phi", "n_e", "n_i")
+    tol = (0.02, 0.04, 0.04)
+    for k in range(3):
+        a, b = sl[k][1:-1], pic[k][1:-1]
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print_case(f"plates physics: {names[k]} rel L2 {err:.4f}")
+        assert err <= tol[k], (names[k], err)
+    # the sheath: phi rises from the grounded plate to the bias (every 5 nodes)
+    phi = pic[0]
+    assert np.all(np.diff(phi[::5]) > 0)
+    # ions reach the grounded plate: their density there is a sizeable
+    # fraction of the mid-gap density, electrons are repelled from it
+    mid = len(phi) // 2
+    assert pic[2][1] > 0.5 * pic[2][mid] and pic[1][1] < 0.1 * pic[1][mid]
+    for s in range(2):
+        assert abs(st_sl["nslots"][s] - st_pic["nslots"][s]) <= 0.5 * st_pic["nslots"][s]
