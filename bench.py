@@ -541,6 +541,9 @@ def run_plates(args, ppc: int = 9000, runs: int = 1) -> dict:
     import workloads
     P = workloads.PLATES_PAPER
     sl = _plates_leg(0.0158, ppc, runs, P["t_steady_us"], P["t_cross_us"])
+    if getattr(args, "plates_leg", "both") == "slpic":  # the SLPIC side alone (for kernel profiles)
+        del sl["profiles"]
+        return {"metric": "SLPIC run of the two-plate sheath to 24 us", "slpic": sl}
     pic = _plates_leg(math.inf, ppc, runs, P["t_steady_us"], P["t_cross_us"])
     agree = {}
     for k in ("phi", "n_e", "n_i"):
@@ -589,21 +592,36 @@ def run_timed(cfg, args, steps, warmup, params):
     g = max(16, params["sort_every"])
     steps = max(g, (steps // g) * g)
     warmup = max(g, (warmup // g) * g)
-    sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"],
-                    sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"], graph_steps=g)
-    sim.step(warmup)
-    torch.cuda.synchronize()
-    sim.profile(True)  # events around each push launch
-    p0 = sim.pushed_total()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pushes = sim.pushed_total() - p0
-    prof = sim.profile_read()["push"]
-    st = sim.status(0)
-    sim.close()
+    # a side stream: the library captures blocks of g steps as HIP graphs
+    # only on a non-default stream.  The timed region replays graphs; a second
+    # context from the same seed then repeats the same steps with HIP events
+    # around every push launch (direct launches), which gives the push
+    # kernel's average duration over the same particle states.
+    def make():
+        return slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"],
+                         sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"],
+                         graph_steps=g)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        sim = make()
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        p0 = sim.pushed_total()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pushes = sim.pushed_total() - p0
+        st = sim.status(0)
+        sim.close()
+        sim = make()
+        sim.step(warmup)
+        sim.profile(True)  # events around each push launch, on the launch stream
+        q0 = sim.pushed_total()
+        sim.step(steps)
+        prof = sim.profile_read()["push"]
+        prof["pushes"] = sim.pushed_total() - q0
+        sim.close()
     return pushes, t1 - t0, prof, st, steps, warmup
 
 
@@ -638,6 +656,8 @@ def main() -> int:
     ap.add_argument("--no-plates", action="store_true", help="leave out the two-plate PIC vs SLPIC experiment")
     ap.add_argument("--plates-ppc", type=int, default=9000, help="g-particles per cell at n0 in the plates experiment")
     ap.add_argument("--plates-runs", type=int, default=1, help="seeds per context in the plates experiment")
+    ap.add_argument("--plates-leg", choices=("both", "slpic"), default="both",
+                    help="slpic: run only the SLPIC side of the plates experiment (for kernel profiles)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the counter workload (copy calibration + direct-launch steps) and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -679,7 +699,7 @@ def main() -> int:
     bpp = BYTES_PER_PUSH[args.precision]
     launches = max(prof["launches"], 1)
     push_ms = prof["ms"] / launches
-    bytes_per_launch = bpp * pushes / launches
+    bytes_per_launch = bpp * prof["pushes"] / launches
     achieved = bytes_per_launch / (push_ms * 1e-3) / 1e9
     traffic = traffic_for(args.ppc, params["chunk"])
     line = {
@@ -727,7 +747,7 @@ def main() -> int:
         p10, e10, prof10, _, s10, _ = run_timed(cfg10, args, 256, 64, params10)
         l10 = max(prof10["launches"], 1)
         ms10 = prof10["ms"] / l10
-        a10 = bpp * p10 / l10 / (ms10 * 1e-3) / 1e9
+        a10 = bpp * prof10["pushes"] / l10 / (ms10 * 1e-3) / 1e9
         line["hbm_variant"] = {"particles": 2 * 2048 * 10 * args.ppc, "value": p10 / e10, "steps": s10,
                                "launch": params10, "push_avg_launch_ms": ms10, "achieved_GBs": a10,
                                "frac": a10 / HBM_PEAK_GBS, "bound": "hbm", "peak": HBM_PEAK_GBS,

@@ -243,11 +243,11 @@ int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, 
 
 /* Kernel timing with HIP events on the launch stream (for roofline
  * accounting).  enable is a bitmask of kernel classes (bit 0 push-deposit,
- * bit 1 unused (the source runs inside the field-solve launch), bit 2 source
- * + field solve, bit 3 sort; 0 = off): an event
- * pair is recorded around every launch of an enabled class in slpic_step (inside
- * the captured graphs when tuning.graph_steps > 0, each replay of a timed
- * region using its own graph and events) and clears previous records.
+ * bit 1 the plates wall injection (the sheath source runs inside the
+ * field-solve launch), bit 2 source + field solve, bit 3 sort; 0 = off): an event
+ * pair is recorded around every launch of an enabled class in slpic_step, and
+ * previous records are cleared.  While profiling is on, slpic_step launches
+ * every kernel directly (no graph replay).
  * slpic_profile_read (sync) returns the summed milliseconds and launch
  * counts per kernel class in that order (arrays of 4). */
 int slpic_profile(void* ctx, int32_t enable);

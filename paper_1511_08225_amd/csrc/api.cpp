@@ -265,14 +265,14 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         P.run_nchunks[r] = (int)P.chunks.size() - P.run_chunk0[r];
     }
     // plates: the wall injection of a step (at most floor(wall_flux) + 1
-    // particles per species) runs in extra workgroups of the push launch
+    // particles per species), kInjectThreads particles per workgroup
     for (int r = 0; r < nruns; ++r) {
         const RunInfo& R = P.runs[r];
         if (R.geom != kGeomPlates) continue;
         for (int s = 0; s < 2; ++s) {
             const double most = std::floor(R.wall_flux[s]) + 1.0;
             if (!(most < 1e9)) return SLPIC_EINVAL;
-            for (int64_t k = 0; k < (int64_t)most; k += t.block) P.injb.push_back(int4{r, s, (int)k, 0});
+            for (int64_t k = 0; k < (int64_t)most; k += kInjectThreads) P.injb.push_back(int4{r, s, (int)k, 0});
         }
     }
     if (P.injb.size() > (size_t)1 << 20) return SLPIC_EINVAL;
@@ -317,14 +317,6 @@ struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
 };
 
-// A captured block of steps with its own event pairs (profiling under graph
-// replay: every replay in a timed region uses a fresh block, so no event is
-// overwritten before it is read).
-struct ProfGraph {
-    hipGraphExec_t exec = nullptr;
-    std::vector<EventPair> ev[4];
-};
-
 struct Context {
     Plan P;
     KArgs a{};
@@ -338,10 +330,6 @@ struct Context {
     int prof_mask = 0;  // kernel classes timed: bit k = class k
     std::vector<EventPair> ev[4];
     size_t ev_used[4] = {0, 0, 0, 0};
-    std::vector<ProfGraph> pgraphs;
-    size_t pg_used = 0;
-    ProfGraph* capturing = nullptr;  // events recorded during a capture go here
-    bool pgraph_failed = false;
     int sample_every = 0;  // in-step moment sampling period (0: off)
     ~Context() {
         if (gexec) hipGraphExecDestroy(gexec);
@@ -350,14 +338,6 @@ struct Context {
                 if (e.a) hipEventDestroy(e.a);
                 if (e.b) hipEventDestroy(e.b);
             }
-        for (auto& g : pgraphs) {
-            if (g.exec) hipGraphExecDestroy(g.exec);
-            for (auto& v : g.ev)
-                for (auto& e : v) {
-                    if (e.a) hipEventDestroy(e.a);
-                    if (e.b) hipEventDestroy(e.b);
-                }
-        }
     }
 };
 
@@ -379,6 +359,10 @@ void l_push(Context* c, bool push, hipStream_t s) {
     else
         launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, s);
 }
+void l_wall_inject(Context* c, hipStream_t s) {
+    if (prec(c) == SLPIC_F32) launch_wall_inject_f32(c->a, s);
+    else launch_wall_inject_f64(c->a, s);
+}
 void l_source_field(Context* c, hipStream_t s) {
     if (prec(c) == SLPIC_F32) launch_source_field_f32(c->a, c->P.nruns, c->source_field_lds, s);
     else launch_source_field_f64(c->a, c->P.nruns, c->source_field_lds, s);
@@ -389,16 +373,6 @@ template <typename F>
 int timed(Context* c, int k, hipStream_t s, F&& f) {
     if (!c->prof || !((c->prof_mask >> k) & 1)) {
         f();
-        return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
-    }
-    if (c->capturing) {  // event record nodes inside the graph being captured
-        EventPair e;
-        HIP_TRY(hipEventCreate(&e.a));
-        HIP_TRY(hipEventCreate(&e.b));
-        c->capturing->ev[k].push_back(e);
-        HIP_TRY(hipEventRecord(e.a, s));
-        f();
-        HIP_TRY(hipEventRecord(e.b, s));
         return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
     }
     if (c->ev_used[k] == c->ev[k].size()) {
@@ -438,6 +412,7 @@ void sample_all(Context* c, hipStream_t s) {
 
 int one_step(Context* c, int64_t local_step, hipStream_t s) {
     int rc;
+    if (c->a.ninjb > 0 && (rc = timed(c, 1, s, [&] { l_wall_inject(c, s); }))) return rc;
     if ((rc = timed(c, 0, s, [&] { l_push(c, true, s); }))) return rc;
     if ((rc = timed(c, 2, s, [&] { l_source_field(c, s); }))) return rc;
     const int se = c->P.tun.sort_every;
@@ -476,37 +451,20 @@ int build_graph(Context* c, hipStream_t s) {
 
 // The next unused profiling graph (captured on first use).  Returns nullptr
 // if event records cannot be captured; the caller then launches directly.
-ProfGraph* next_prof_graph(Context* c, hipStream_t s) {
-    if (c->pgraph_failed) return nullptr;
-    if (c->pg_used == c->pgraphs.size()) {
-        c->pgraphs.emplace_back();
-        ProfGraph* pg = &c->pgraphs.back();
-        c->capturing = pg;
-        int rc = capture_steps(c, s, &pg->exec);
-        c->capturing = nullptr;
-        if (rc != SLPIC_OK) {
-            for (auto& v : pg->ev)
-                for (auto& e : v) {
-                    if (e.a) hipEventDestroy(e.a);
-                    if (e.b) hipEventDestroy(e.b);
-                }
-            c->pgraphs.pop_back();
-            c->pgraph_failed = true;
-            return nullptr;
-        }
-    }
-    return &c->pgraphs[c->pg_used++];
-}
-
 Context* ctx_of(void* p) { return static_cast<Context*>(p); }
 
+// The synchronous copies of the "sync" calls wait for the whole device
+// first: work enqueued on a non-blocking stream is not ordered with the
+// default stream that hipMemcpy uses.
 int copy_d2h(void* dst, const void* src, size_t bytes) {
     if (!bytes) return SLPIC_OK;
+    HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
     return SLPIC_OK;
 }
 int copy_h2d(void* dst, const void* src, size_t bytes) {
     if (!bytes) return SLPIC_OK;
+    HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return SLPIC_OK;
 }
@@ -634,29 +592,22 @@ int slpic_step(void* ctx, int32_t nsteps, void* stream) {
     if (!c || nsteps < 0) return SLPIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int se = c->P.tun.sort_every;
-    const bool graphs = c->P.tun.graph_steps > 0 && s != nullptr;
+    // graphs on a non-default stream; profiled steps launch directly (event
+    // timings of graph-recorded events are not available)
+    const bool graphs = c->P.tun.graph_steps > 0 && s != nullptr && !c->prof;
     int32_t done = 0;
     while (done < nsteps) {
         const int gl = c->P.tun.graph_steps;
         if (graphs && nsteps - done >= gl && (se == 0 || c->steps_done % se == 0) &&
             (c->sample_every == 0 || c->steps_done % c->sample_every == 0)) {
-            hipGraphExec_t ex = nullptr;
-            if (c->prof) {
-                ProfGraph* pg = next_prof_graph(c, s);
-                if (pg) ex = pg->exec;
-            } else {
-                if (!c->gexec) {
-                    int rc = build_graph(c, s);
-                    if (rc) return rc;
-                }
-                ex = c->gexec;
+            if (!c->gexec) {
+                int rc = build_graph(c, s);
+                if (rc) return rc;
             }
-            if (ex) {
-                HIP_TRY(hipGraphLaunch(ex, s));
-                c->steps_done += gl;
-                done += gl;
-                continue;
-            }
+            HIP_TRY(hipGraphLaunch(c->gexec, s));
+            c->steps_done += gl;
+            done += gl;
+            continue;
         }
         int rc = one_step(c, c->steps_done, s);
         if (rc) return rc;
@@ -891,19 +842,6 @@ int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, 
     return SLPIC_OK;
 }
 
-static void drop_prof_graphs(Context* c) {
-    for (auto& g : c->pgraphs) {
-        if (g.exec) hipGraphExecDestroy(g.exec);
-        for (auto& v : g.ev)
-            for (auto& e : v) {
-                if (e.a) hipEventDestroy(e.a);
-                if (e.b) hipEventDestroy(e.b);
-            }
-    }
-    c->pgraphs.clear();
-    c->pg_used = 0;
-}
-
 int slpic_set_sampling(void* ctx, int32_t every) {
     Context* c = ctx_of(ctx);
     if (!c || every < 0) return SLPIC_EINVAL;
@@ -915,7 +853,6 @@ int slpic_set_sampling(void* ctx, int32_t every) {
         hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
     }
-    drop_prof_graphs(c);
     c->sample_every = every;
     return SLPIC_OK;
 }
@@ -924,11 +861,9 @@ int slpic_profile(void* ctx, int32_t enable) {
     Context* c = ctx_of(ctx);
     if (!c) return SLPIC_EINVAL;
     HIP_TRY(hipDeviceSynchronize());
-    if (c->prof_mask != (enable & 15)) drop_prof_graphs(c);  // they hold the old event layout
     c->prof = (enable & 15) != 0;
     c->prof_mask = enable & 15;
     for (auto& u : c->ev_used) u = 0;
-    c->pg_used = 0;
     return SLPIC_OK;
 }
 
@@ -945,13 +880,6 @@ int slpic_profile_read(void* ctx, double* h_ms, int64_t* h_launches) {
             sum += ms;
             ++n;
         }
-        for (size_t g = 0; g < c->pg_used; ++g)
-            for (auto& e : c->pgraphs[g].ev[k]) {
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
-                sum += ms;
-                ++n;
-            }
         h_ms[k] = sum;
         h_launches[k] = n;
     }

@@ -16,6 +16,7 @@ namespace slpic {
                                    const void* c2, const void* acc, void* out, int* iters,             \
                                    hipStream_t s);                                                     \
     void launch_source_field_##sfx(const KArgs& a, int nruns, size_t lds, hipStream_t s);              \
+    void launch_wall_inject_##sfx(const KArgs& a, hipStream_t s);                                      \
     void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \
                               double* out, int per_run, hipStream_t s);                                \
     void launch_sort_hist_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);     \

@@ -16,7 +16,8 @@ constexpr int kPurposeWall = 5;       // plates: a particle entering through x =
 constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
 constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
 constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers
-constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the push LDS window
+constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the injection LDS window
+constexpr int kInjectThreads = 128;     // plates: particles per wall-injection workgroup
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
 constexpr int kCountSlots = 64;    // spread slots of the per-step particle counters
 

@@ -381,6 +381,32 @@ def test_in_step_sampling_matches_host_sampling(gpu_lib):
         b.close()
 
 
+def test_profile_counts_every_launch(gpu_lib):
+    """Kernel timing: one event pair per push and per source + field launch
+    of every profiled step (graph replay is off while profiling), sorts every
+    sort_every steps; reading clears nothing until the next enable."""
+    import torch
+    cfg = workloads.small_sheath(seed=12)
+    with torch.cuda.stream(torch.cuda.Stream()):
+        sim = gpu_lib.Sim(cfg, precision="f32", sort_every=4, graph_steps=8)
+        sim.step(8)
+        sim.profile(1 | 4)
+        sim.step(16)
+        p = sim.profile_read()
+        assert p["push"]["launches"] == 16 and p["field"]["launches"] == 16
+        assert p["sort"]["launches"] == 0  # bit 3 not enabled
+        assert p["push"]["ms"] > 0 and p["field"]["ms"] > 0
+        sim.profile(1 | 4 | 8)
+        sim.step(8)
+        p = sim.profile_read()
+        assert p["push"]["launches"] == 8 and p["sort"]["launches"] == 2
+        sim.profile(0)
+        sim.step(8)
+        assert sim.profile_read()["push"]["launches"] == 0
+        assert sim.status(0)["step"] == 40
+        sim.close()
+
+
 def test_capacity_overflow_sets_sticky_flag(gpu_lib):
     cfg = workloads.small_sheath(capacity_factor=1.0, seed=10)
     sim = gpu_lib.Sim(cfg, precision="f64", sort_every=0)
