@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "slpic_oracle.c")
 _LIB = os.path.join(_HERE, "libslpic_oracle.so")
 
 BETA_STEP, BETA_SMOOTH = 0, 1
-GEOM_SHEATH, GEOM_PLATES = 0, 1
+GEOM_SHEATH, GEOM_PLATES, GEOM_PERIODIC = 0, 1, 2
 KICK_EXACT, KICK_MMP = 0, 1
 
 
@@ -128,6 +128,10 @@ def lib():
             "orc_wall_inject_particle": (None, [ctypes.POINTER(_Config), _I32, ctypes.c_uint32, ctypes.c_uint32,
                                                 _PD]),
             "orc_wall_flux_per_step": (_D, [ctypes.POINTER(_Config), _I32]),
+            "orc_poisson1d_periodic": (None, [_I32, _D, _PD, _PD, _PD]),
+            "orc_wrap_periodic": (_D, [_D, _I32]),
+            "orc_slpic_plasma_freq2": (_D, [_I32, _D, _D]),
+            "orc_slpic_dispersion": (_D, [_I32, _D, _D, _D]),
             "orc_create": (_VP, [ctypes.POINTER(_Config)]),
             "orc_destroy": (None, [_VP]),
             "orc_load": (None, [_VP]),
@@ -142,6 +146,7 @@ def lib():
             "orc_step_index": (_I64, [_VP]),
             "orc_acc_e": (_D, [_VP]),
             "orc_acc_flux": (_D, [_VP, _I32]),
+            "orc_monitor": (_D, [_VP]),
             "orc_absorbed_total": (_I64, [_VP, _I32]),
             "orc_injected_total": (_I64, [_VP, _I32]),
             "orc_get_particles": (None, [_VP, _I32, _PD, _PD, _PD, _PD]),
@@ -221,7 +226,7 @@ def make_config(cfg: dict) -> _Config:
     c.capacity_factor = float(cfg.get("capacity_factor", 1.5))
     c.steady_window = int(cfg.get("steady_window", 0))
     c.steady_tol = float(cfg.get("steady_tol", 0.0))
-    c.geometry = {"sheath": GEOM_SHEATH, "plates": GEOM_PLATES}[cfg.get("geometry", "sheath")]
+    c.geometry = {"sheath": GEOM_SHEATH, "plates": GEOM_PLATES, "periodic": GEOM_PERIODIC}[cfg.get("geometry", "sheath")]
     c.bias = float(cfg.get("bias", 0.0))
     return c
 
@@ -344,6 +349,32 @@ def wall_flux_per_step(cfg: dict, s: int) -> float:
     return lib().orc_wall_flux_per_step(ctypes.byref(c), s)
 
 
+def poisson1d_periodic(nx: int, dx: float, Q: np.ndarray):
+    """Periodic box: node nx is the image of node 0 (its charge folds onto
+    node 0), the mean charge is removed, gauge phi(0) = 0."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    phi, E = np.zeros(nx + 1), np.zeros(nx + 1)
+    lib().orc_poisson1d_periodic(nx, dx, _dp(Q), _dp(phi), _dp(E))
+    return phi, E
+
+
+def wrap_periodic(xt: float, nx: int) -> float:
+    return lib().orc_wrap_periodic(float(xt), int(nx))
+
+
+def slpic_dispersion(kind, u: float, k: float, vt: float = 1.0) -> float:
+    """The real frequency (omega_p = 1) of the mode k from the full
+    dispersion relation of speed-limited particles (root above k u)."""
+    kk = {"step": 0, "smooth": 1}[kind] if isinstance(kind, str) else int(kind)
+    return lib().orc_slpic_dispersion(kk, float(u), float(vt), float(k))
+
+
+def slpic_plasma_freq2(kind, u: float, vt: float = 1.0) -> float:
+    """(omega_s/omega_p)^2 = <(beta v_x)^2>/v_t^2 over the 3D Maxwellian."""
+    k = {"step": 0, "smooth": 1}[kind] if isinstance(kind, str) else int(kind)
+    return lib().orc_slpic_plasma_freq2(k, float(u), float(vt))
+
+
 # ----------------------------------------------------------------------- run
 class Run:
     """One 1D3V SLPIC run on the CPU (FP64)."""
@@ -402,6 +433,11 @@ class Run:
     @property
     def acc_e(self) -> float:
         return lib().orc_acc_e(self._h)
+
+    def monitor(self) -> float:
+        """The monitored value: Phi_w (sheath), phi(L/2) (plates), the
+        fundamental sine amplitude of E (periodic)."""
+        return lib().orc_monitor(self._h)
 
     def acc_flux(self) -> list:
         """Plates: the fractional wall injection carried over, per species."""

@@ -485,6 +485,137 @@ void orc_poisson1d_plates(int32_t nx, double dx, const double* Q, double bias, d
     free(dp);
 }
 
+/* Periodic box (plasma-oscillation section): nodes 0..nx-1 with node nx the
+ * image of node 0.  The charge of node nx is folded onto node 0, the mean
+ * charge (a uniform neutralising background) is removed, and with the gauge
+ * phi_0 = 0 periodicity gives phi_nx = 0 too: the rows of nodes 1..nx-1 are
+ * then the two-plate system with zero bias (the row of node 0 follows from
+ * them because the charge sums to zero).  E by centred differences around
+ * the ring; node nx repeats node 0. */
+void orc_poisson1d_periodic(int32_t nx, double dx, const double* Q, double* phi, double* E) {
+    double* Qp = (double*)calloc((size_t)nx + 1, sizeof(double));
+    double tot = 0.0;
+    for (int j = 0; j < nx; ++j) {
+        Qp[j] = Q[j] + (j == 0 ? Q[nx] : 0.0);
+        tot += Qp[j];
+    }
+    double mean = tot / (double)nx;
+    for (int j = 0; j < nx; ++j) Qp[j] -= mean;
+    Qp[nx] = 0.0;
+    orc_poisson1d_plates(nx, dx, Qp, 0.0, phi, E);
+    phi[nx] = phi[0];
+    E[0] = -(phi[1] - phi[nx - 1]) / (2.0 * dx);
+    for (int j = 1; j < nx; ++j) E[j] = -(phi[j + 1] - phi[j - 1]) / (2.0 * dx);
+    E[nx] = E[0];
+    free(Qp);
+}
+
+double orc_wrap_periodic(double xt, int32_t nx) {
+    double L = (double)nx;
+    if (xt < 0.0 || xt >= L) {
+        xt -= L * floor(xt / L);
+        if (xt >= L) xt = 0.0; /* a tiny negative position rounds onto L: its image is 0 */
+    }
+    return xt;
+}
+
+/* <(beta v_x)^2>/v_t^2 for the 3D Maxwellian: beta depends on the speed
+ * only, so <beta^2 v_x^2> = <beta^2 s^2>/3 over the Maxwell speed density
+ * 4 pi s^2 (2 pi vt^2)^(-3/2) exp(-s^2 / 2 vt^2); the speed integral is taken
+ * by the composite Simpson rule on [0, 12 vt] with 24000 panels (its tail
+ * is below 1e-28), split at s = u for the step form's kink. */
+static double simpson_p(double (*f)(double, const double*), const double* p, double a, double b, int n) {
+    if (b <= a) return 0.0;
+    if (n % 2) n += 1;
+    double h = (b - a) / n, sum = f(a, p) + f(b, p);
+    for (int i = 1; i < n; ++i) sum += f(a + i * h, p) * ((i % 2) ? 4.0 : 2.0);
+    return sum * h / 3.0;
+}
+
+static double pf2_integrand(double s, const double* p) {
+    /* p = {kind, u, vt} */
+    double b = beta_of_s2((int)p[0], p[1], s * s);
+    return b * b * s * s / 3.0 * maxwell_speed_pdf(s / p[2]) / p[2];
+}
+
+double orc_slpic_plasma_freq2(int kind, double u, double vt) {
+    double p[3] = {(double)kind, u, vt};
+    double top = 12.0 * vt;
+    double val;
+    if (isinf(u) || u >= top) {
+        val = simpson_p(pf2_integrand, p, 0.0, top, 24000);
+    } else {
+        int n1 = (int)(24000.0 * u / top) + 2;
+        val = simpson_p(pf2_integrand, p, 0.0, u, n1) + simpson_p(pf2_integrand, p, u, top, 24000 - n1 + 2);
+    }
+    return val / (vt * vt);
+}
+
+/* The full long-time dispersion relation of the plasma-oscillation section
+ * for 1D perturbations exp(i(kx - wt)) of a uniform Maxwellian (omega_p = 1):
+ *   D(w) = 1 - (1/w^2) < (beta^2 + (d beta/d v_x) w/k) / (1 - k beta v_x/w)^2 >.
+ * beta depends on the speed s only: v_x = s mu, d beta/d v_x = beta'(s) mu,
+ * and the average over the direction cosine mu (uniform on [-1, 1]) is
+ * done in closed form with c = k beta(s) s / w < 1:
+ *   (1/2) int (A + B mu)/(1 - c mu)^2 dmu = A/(1 - c^2)
+ *       + (B/(2c^2)) (2c/(1 - c^2) + ln((1 - c)/(1 + c))),
+ * with A = beta(s)^2 and B = beta'(s) w/k; for c < 1e-3 the
+ * bracket over c^2 is replaced by its series 4c/3 + 8c^3/5.  The speed integral is
+ * the composite Simpson rule on [0, 12 vt] (split at u).  Since beta s <= u
+ * for both speed limits, no particle resonates once w > k u, and D rises
+ * from -inf (w -> k u) to 1 (w -> inf): the root is found by bisection.
+ * For u = inf this is the fluid limit of the resonant relation (no Landau
+ * term), used only where k v_t << w. */
+static double beta_prime(int kind, double u, double s) {
+    if (isinf(u)) return 0.0;
+    if (kind == ORC_BETA_SMOOTH) return -(s / (u * u)) * pow(1.0 + s * s / (u * u), -1.5);
+    return s <= u ? 0.0 : -u / (s * s);
+}
+
+static double disp_integrand(double s, const double* p) {
+    /* p = {kind, u, vt, k, w} */
+    int kind = (int)p[0];
+    double u = p[1], vt = p[2], k = p[3], w = p[4];
+    double b = beta_of_s2(kind, u, s * s);
+    double A = b * b, B = beta_prime(kind, u, s) * w / k;
+    double c = k * b * s / w;
+    double mu_avg;
+    if (c < 1e-3) {
+        mu_avg = A / (1.0 - c * c) + (B / 2.0) * (4.0 * c / 3.0 + 8.0 * c * c * c / 5.0);
+    } else {
+        mu_avg = A / (1.0 - c * c) + (B / (2.0 * c * c)) * (2.0 * c / (1.0 - c * c) + log((1.0 - c) / (1.0 + c)));
+    }
+    return mu_avg * maxwell_speed_pdf(s / vt) / vt;
+}
+
+static double dispersion_D(int kind, double u, double vt, double k, double w) {
+    double p[5] = {(double)kind, u, vt, k, w};
+    double top = 12.0 * vt;
+    double avg;
+    if (isinf(u) || u >= top) {
+        avg = simpson_p(disp_integrand, p, 0.0, top, 24000);
+    } else {
+        int n1 = (int)(24000.0 * u / top) + 2;
+        /* the step form's d beta/d|v| jumps at u: the upper piece starts just
+         * above it so that its first node takes the right-hand value */
+        avg = simpson_p(disp_integrand, p, 0.0, u, n1) +
+              simpson_p(disp_integrand, p, nextafter(u, INFINITY), top, 24000 - n1 + 2);
+    }
+    return 1.0 - avg / (w * w);
+}
+
+double orc_slpic_dispersion(int kind, double u, double vt, double k) {
+    double vmax = isinf(u) ? 12.0 * vt : u;  /* the largest beta |v| */
+    double lo = k * vmax * (1.0 + 1e-12) + 1e-300, hi = 1.0;
+    while (dispersion_D(kind, u, vt, k, hi) < 0.0) hi *= 2.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (dispersion_D(kind, u, vt, k, mid) < 0.0) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* Expected g-particles entering through the plate at x = L per step: the
  * one-sided flux n0 v_t / sqrt(2 pi) of a stationary Maxwellian (n0 = 1)
  * times dt, over the weight (each entering g-particle carries w physical
@@ -627,6 +758,8 @@ static void solve_fields(orc_run* r) {
         for (int s = 0; s < r->cfg.nspecies; ++s) Qt[j] += r->Q[s][j];
     if (r->cfg.geometry == ORC_GEOM_PLATES)
         orc_poisson1d_plates(r->cfg.nx, r->cfg.dx, Qt, r->cfg.bias, r->phi, r->E);
+    else if (r->cfg.geometry == ORC_GEOM_PERIODIC)
+        orc_poisson1d_periodic(r->cfg.nx, r->cfg.dx, Qt, r->phi, r->E);
     else
         orc_poisson1d(r->cfg.nx, r->cfg.dx, Qt, r->phi, r->E);
     free(Qt);
@@ -837,13 +970,21 @@ static void inject(orc_run* r, int s, int64_t count) {
     r->injected_total[s] += count;
 }
 
-/* The potential the steady detector watches: Phi_w = phi(0) - phi(L) for
- * the sheath; for the plates, whose end potentials are fixed, phi at the
- * mid-plane node. */
+/* The quantity the steady detector and the history watch: Phi_w = phi(0) -
+ * phi(L) for the sheath; for the plates, whose end potentials are fixed, phi
+ * at the mid-plane node; for the periodic box, E at node nx/4 (the peak of
+ * the field of a cos(2 pi x/L) density perturbation). */
 static double orc_monitor_potential(const orc_run* r) {
     if (r->cfg.geometry == ORC_GEOM_PLATES) return r->phi[r->cfg.nx / 2];
+    if (r->cfg.geometry == ORC_GEOM_PERIODIC) {
+        double a = 0.0;
+        for (int j = 0; j < r->cfg.nx; ++j) a += r->E[j] * sin(TWO_PI * (double)j / (double)r->cfg.nx);
+        return 2.0 * a / (double)r->cfg.nx;
+    }
     return r->phi[0] - r->phi[r->cfg.nx];
 }
+
+double orc_monitor(const orc_run* r) { return orc_monitor_potential(r); }
 
 /* One step of Eq. (A2a-d). */
 void orc_step(orc_run* r, int32_t nsteps) {
@@ -870,7 +1011,9 @@ void orc_step(orc_run* r, int32_t nsteps) {
                 double b = beta_of_s2(cfg->beta_kind, cfg->u, norm2(v1));
                 double xn = xt + b * v1[0] * dtdx;
                 int left_out = 0;
-                if (xn < 0.0) {
+                if (cfg->geometry == ORC_GEOM_PERIODIC) {
+                    xn = orc_wrap_periodic(xn, cfg->nx);
+                } else if (xn < 0.0) {
                     if (cfg->geometry == ORC_GEOM_PLATES) {
                         left_out = 1; /* absorbing plate */
                     } else {      /* symmetry plane: specular reflection */
@@ -906,7 +1049,8 @@ void orc_step(orc_run* r, int32_t nsteps) {
                 r->n[s] += m;
                 r->injected_total[s] += m;
             }
-        } else if (cfg->nspecies == 2) { /* thermal source: ion-loss-balanced pairs */
+        } else if (cfg->nspecies == 2 && cfg->geometry == ORC_GEOM_SHEATH) {
+            /* thermal source: ion-loss-balanced pairs */
             int64_t ni = absorbed[1];
             r->acc_e += (double)ni * (r->w[1] / r->w[0]);
             int64_t ne = (int64_t)floor(r->acc_e);

@@ -33,10 +33,12 @@ enum { ORC_KICK_EXACT = 0, ORC_KICK_MMP = 1 };
 enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2, ORC_PURPOSE_WARM_COUNT = 3, ORC_PURPOSE_WARM = 4,
        ORC_PURPOSE_WALL = 5 };
 /* Geometry: the sheath (symmetry plane at x = 0, grounded absorbing wall at
- * x = L, volume pair source) or the two conducting plates of Sec. IV
+ * x = L, volume pair source), the two conducting plates of Sec. IV
  * (phi(0) = 0, phi(L) = bias, both absorbing, half-Maxwellian flux injected
- * from the plate at x = L; the box starts empty). */
-enum { ORC_GEOM_SHEATH = 0, ORC_GEOM_PLATES = 1 };
+ * from the plate at x = L; the box starts empty), or a periodic box (the
+ * uniform plasma of the plasma-oscillation section: particles wrap, no
+ * source, the field of the charge less its mean, gauge phi(0) = 0). */
+enum { ORC_GEOM_SHEATH = 0, ORC_GEOM_PLATES = 1, ORC_GEOM_PERIODIC = 2 };
 
 typedef struct {
     double charge, mass, temperature;
@@ -61,7 +63,7 @@ typedef struct {
     int32_t steady_window; /* steps per wall-potential window; 0: max(1, nx/4) */
     int32_t pad;
     double steady_tol;     /* relative spread of three window means; 0: 0.02 */
-    int32_t geometry;      /* ORC_GEOM_SHEATH / ORC_GEOM_PLATES               */
+    int32_t geometry;      /* ORC_GEOM_SHEATH / ORC_GEOM_PLATES / ORC_GEOM_PERIODIC */
     int32_t pad2;
     double bias;           /* plates: phi(L) in T_e/e                         */
 } orc_config;
@@ -111,6 +113,17 @@ void orc_poisson1d(int32_t nx, double dx, const double* Q, double* phi, double* 
 void orc_poisson1d_plates(int32_t nx, double dx, const double* Q, double bias, double* phi, double* E);
 void orc_wall_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step, double out[4]);
 double orc_wall_flux_per_step(const orc_config* cfg, int s);
+void orc_poisson1d_periodic(int32_t nx, double dx, const double* Q, double* phi, double* E);
+/* x in [0, nx) after a periodic move. */
+double orc_wrap_periodic(double xt, int32_t nx);
+/* (omega_s / omega_p)^2 = <(beta v_x)^2> / v_t^2 over the Maxwellian of
+ * thermal speed vt (the long-wavelength plasma frequency of speed-limited
+ * particles, plasma-oscillation section). */
+double orc_slpic_plasma_freq2(int kind, double u, double vt);
+/* The real root w > k u (omega_p = 1) of the full dispersion relation of
+ * speed-limited particles for 1D perturbations exp(i(kx - wt)) of a uniform
+ * Maxwellian (plasma-oscillation section). */
+double orc_slpic_dispersion(int kind, double u, double vt, double k);
 
 /* --- run ----------------------------------------------------------------- */
 orc_run* orc_create(const orc_config* cfg);
@@ -142,6 +155,9 @@ int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const d
 void orc_set_counters(orc_run* r, int64_t step, double acc_e);
 /* Plates: the fractional wall injection carried over, per species. */
 double orc_acc_flux(const orc_run* r, int32_t s);
+/* The monitored value after the last field solve: Phi_w (sheath), phi at
+ * node nx/2 (plates), the fundamental sine amplitude of E (periodic). */
+double orc_monitor(const orc_run* r);
 void orc_get_grid(const orc_run* r, double* Q0, double* Q1, double* phi, double* E);
 void orc_get_steady(const orc_run* r, orc_steady* out);
 

@@ -137,6 +137,46 @@ def plates_steps(cfg: dict, t_us: float) -> int:
     return int(round(t_us * PAPER_OMEGA_PE_US / cfg["dt"]))
 
 
+def langmuir_box(u_over_vte: float, nx: int = 256, ppc: int = 1000, dx: float = 0.5, seed: int = 0,
+                 beta_kind: str = "step", sort_every: int = 16) -> dict:
+    """A uniform Maxwellian plasma in a periodic box (the plasma-oscillation
+    section): nx cells of dx = 0.5 Debye lengths (k lambda_D = 2 pi/(nx dx) =
+    0.049 at 256 cells for the fundamental mode), electrons at T_e = 1 and
+    argon ions (40 amu, T_i = T_e/20) loaded uniformly, ppc g-particles per
+    cell per species.  SLPIC at u = u_over_vte * v_te takes dt = dx/u (the
+    paper's choice of step); u = inf (PIC) takes dt = dx/(5 v_te)."""
+    u = math.inf if math.isinf(u_over_vte) else float(u_over_vte)
+    dt = dx / 5.0 if math.isinf(u) else dx / u
+    return {
+        "nx": int(nx), "dx": float(dx), "dt": float(dt), "u": u, "beta_kind": beta_kind,
+        "species": species(20.0, 40.0, ppc), "source_cells": 4, "seed": int(seed), "run": 0,
+        "sort_every": int(sort_every), "sort_bucket": 1, "capacity_factor": 1.0, "geometry": "periodic",
+        "bias": 0.0, "steady_window": 0, "steady_tol": 0.0,
+    }
+
+
+def langmuir_displacement(x: np.ndarray, nx: int, amplitude: float) -> np.ndarray:
+    """The initial perturbation of the periodic box: positions (in cells)
+    moved by xi = (amplitude nx / 2 pi) sin(2 pi x / nx), which leaves the
+    density n0 (1 - amplitude cos(2 pi x / nx)) to first order and the field
+    E(L/4) = amplitude L / (2 pi) (for electrons of charge -1); wrapped into
+    [0, nx)."""
+    xi = amplitude * nx / (2.0 * math.pi) * np.sin(2.0 * math.pi * x / nx)
+    y = x + xi
+    return np.mod(y, nx)
+
+
+def zero_crossing_frequency(t: np.ndarray, y: np.ndarray) -> float:
+    """Angular frequency of an oscillating series from its zero crossings
+    (linear interpolation between samples): pi per half period."""
+    s = np.sign(y)
+    idx = np.nonzero(s[:-1] * s[1:] < 0)[0]
+    if len(idx) < 3:
+        return float("nan")
+    tc = t[idx] - y[idx] * (t[idx + 1] - t[idx]) / (y[idx + 1] - y[idx])
+    return math.pi * (len(tc) - 1) / (tc[-1] - tc[0])
+
+
 def wave_test(v0_over_vphi: float, n: int = 100_000, seed: int = 0, cells: int = 100, periods_ramp: float = 20.0,
               phi_max: float = 0.1, beta_kind: str = "step"):
     """Test electrons in a prescribed traveling wave phi0(t) sin(k(x - v_phi t))
