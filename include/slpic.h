@@ -26,6 +26,15 @@
  * v_x = -v_t sqrt(-2 ln(1 - U)), v_y and v_z Maxwellian, placed a uniform
  * fraction of the step's travel beta(|v|) |v_x| dt inside the plate (at most
  * source_cells cells).  The monitored potential is phi at node nx/2.
+ *
+ * Geometry SLPIC_GEOM_PERIODIC (the uniform plasma of the plasma-oscillation
+ * section): positions wrap around [0, L), nothing is absorbed or injected;
+ * node nx is the image of node 0 (the deposit on it is folded onto node 0 in
+ * the solve), the mean charge is removed (a neutralising background) and
+ * phi(0) = 0 fixes the gauge; E by centred differences around the ring.
+ * The monitored value (history, steady detector, wall_potential) is the
+ * fundamental sine amplitude of E, (2/nx) sum_{j<nx} E_j sin(2 pi j/nx).  slpic_moments uses the sheath's half volumes at both end
+ * nodes, so its values at nodes 0 and nx are not those of a periodic box.
  * Normalised units: x in electron Debye lengths, t in 1/omega_pe, v in the
  * electron thermal speed, phi in T_e/e, density in n0; e = m_e = eps0 = 1.
  *
@@ -75,7 +84,7 @@ enum { SLPIC_BETA_STEP = 0, SLPIC_BETA_SMOOTH = 1 };
 enum { SLPIC_F32 = 0, SLPIC_F64 = 1 };
 
 /* Geometry of a run (slpic_run_config.geometry). */
-enum { SLPIC_GEOM_SHEATH = 0, SLPIC_GEOM_PLATES = 1 };
+enum { SLPIC_GEOM_SHEATH = 0, SLPIC_GEOM_PLATES = 1, SLPIC_GEOM_PERIODIC = 2 };
 
 /* Error flag bits reported in slpic_run_status.error_flags. */
 enum { SLPIC_FLAG_CAPACITY = 1, SLPIC_FLAG_NUMERIC = 2 };
@@ -110,8 +119,9 @@ typedef struct {
                            /* cell is loaded from the Maxwellian drifting at     */
                            /* V = Gamma/n (|V| <= 4 vt) with n dx <1/beta>/w     */
                            /* g-particles sampled as f/beta (Eq. 5)             */
-    int32_t geometry;      /* SLPIC_GEOM_SHEATH (0) or SLPIC_GEOM_PLATES; plates */
-                           /* need nx <= 16384 and no warm_profile               */
+    int32_t geometry;      /* SLPIC_GEOM_SHEATH (0), SLPIC_GEOM_PLATES or       */
+                           /* SLPIC_GEOM_PERIODIC; the last two need nx <= 16384 */
+                           /* and no warm_profile                               */
     int32_t reserved;
     double bias;           /* SLPIC_GEOM_PLATES: phi(L) in T_e/e; else unused   */
 } slpic_run_config;
@@ -139,7 +149,8 @@ typedef struct {
     int64_t injected_total[2]; /* particles injected by the source since load      */
     double acc_e;              /* fractional electron injection carried over       */
     double wall_potential;     /* phi(0) - phi(L) after the last field solve       */
-                               /* (plates: phi at node nx/2)                        */
+                               /* (plates: phi at node nx/2; periodic: the sine     */
+                               /* amplitude of E's fundamental mode)               */
     int32_t error_flags;       /* SLPIC_FLAG_* bits (sticky)                       */
     int32_t fixed_bits;        /* F32: fraction bits of the position fixed point   */
     double weight[2];          /* macroparticle weight per species, dx Z / ppc     */

@@ -516,6 +516,7 @@ double orc_wrap_periodic(double xt, int32_t nx) {
         xt -= L * floor(xt / L);
         if (xt >= L) xt = 0.0; /* a tiny negative position rounds onto L: its image is 0 */
     }
+    if (!(xt >= 0.0 && xt < L)) xt = -1.0; /* no image (a non-finite move): the slot is dropped */
     return xt;
 }
 

@@ -169,10 +169,11 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             c.source_cells < 1 || c.source_cells > c.nx ||
             (c.beta_kind != SLPIC_BETA_STEP && c.beta_kind != SLPIC_BETA_SMOOTH))
             return SLPIC_EINVAL;
-        const bool plates = c.geometry == SLPIC_GEOM_PLATES;
-        if ((c.geometry != SLPIC_GEOM_SHEATH && !plates) ||
+        const bool plates = c.geometry == SLPIC_GEOM_PLATES, periodic = c.geometry == SLPIC_GEOM_PERIODIC;
+        if ((c.geometry != SLPIC_GEOM_SHEATH && !plates && !periodic) ||
             (plates && (c.warm_profile || c.nx > kPlatesMaxCells || c.source_cells > kPlatesMaxSource ||
-                        !std::isfinite(c.bias))))
+                        !std::isfinite(c.bias))) ||
+            (periodic && (c.warm_profile || c.nx > kPlatesMaxCells)))
             return SLPIC_EINVAL;
         RunInfo& R = P.runs[r];
         R.nx = c.nx;
@@ -231,7 +232,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             hoff += (int64_t)R.nkeys * R.ntiles[s];
         }
         R.inj_ratio = R.w[1] / R.w[0];
-        R.geom = plates ? kGeomPlates : kGeomSheath;
+        R.geom = plates ? kGeomPlates : periodic ? kGeomPeriodic : kGeomSheath;
         R.bias = plates ? c.bias : 0.0;
         if (c.steady_window < 0 || !(c.steady_tol >= 0.0)) return SLPIC_EINVAL;
         R.steady_window = c.steady_window > 0 ? c.steady_window : std::max(1, c.nx / 4);

@@ -15,6 +15,7 @@ constexpr int kPurposeWarm = 4;       // warm load: one particle
 constexpr int kPurposeWall = 5;       // plates: a particle entering through x = L
 constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
 constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
+constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
 constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers
 constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the injection LDS window
 constexpr int kInjectThreads = 128;     // plates: particles per wall-injection workgroup

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslpic.so")
 
 SLPIC_F32, SLPIC_F64 = 0, 1
-GEOM_SHEATH, GEOM_PLATES = 0, 1
+GEOM_SHEATH, GEOM_PLATES, GEOM_PERIODIC = 0, 1, 2
 BETA_STEP, BETA_SMOOTH = 0, 1
 FLAG_CAPACITY, FLAG_NUMERIC = 1, 2
 PROFILE_CLASSES = ("push", "inject", "field", "sort")
@@ -206,7 +206,8 @@ def run_config(cfg: dict) -> RunConfig:
     c.steady_window = int(cfg.get("steady_window", 0))
     c.steady_tol = float(cfg.get("steady_tol", 0.0))
     geom = cfg.get("geometry", "sheath")
-    c.geometry = {"sheath": GEOM_SHEATH, "plates": GEOM_PLATES}[geom] if isinstance(geom, str) else int(geom)
+    c.geometry = ({"sheath": GEOM_SHEATH, "plates": GEOM_PLATES, "periodic": GEOM_PERIODIC}[geom]
+                  if isinstance(geom, str) else int(geom))
     c.bias = float(cfg.get("bias", 0.0))
     return c
 

@@ -133,9 +133,28 @@ def test_plates_planning_validates_configs():
     bad = slpic.run_config(cfg)
     bad.warm_profile = prof.ctypes.data
     assert L.slpic_workspace_bytes(ctypes.byref(bad), 1, ctypes.byref(t)) == 0
-    for field, val in (("geometry", 2), ("bias", float("nan")), ("nx", 16385)):
+    for field, val in (("geometry", 3), ("bias", float("nan")), ("nx", 16385)):
         bad = slpic.run_config(cfg)
         setattr(bad, field, val)
         assert L.slpic_workspace_bytes(ctypes.byref(bad), 1, ctypes.byref(t)) == 0, field
     assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(slpic.Tuning2D())) == 0
     assert "slpic_set_flux_counters" in _declared_functions()
+
+
+def test_periodic_planning_validates_configs():
+    import torch  # noqa: F401
+    import numpy as np
+    import workloads
+    from paper_1511_08225_amd import slpic
+    L = slpic.lib()
+    t = slpic.tuning(precision="f32", sort_every=16)
+    cfg = workloads.langmuir_box(0.25, nx=256, ppc=10)
+    good = slpic.run_config(cfg)
+    assert good.geometry == slpic.GEOM_PERIODIC
+    assert L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(t)) > 0
+    big = slpic.run_config(dict(cfg, nx=16385))
+    assert L.slpic_workspace_bytes(ctypes.byref(big), 1, ctypes.byref(t)) == 0
+    prof = np.zeros((5, 256))
+    warm = slpic.run_config(cfg)
+    warm.warm_profile = prof.ctypes.data
+    assert L.slpic_workspace_bytes(ctypes.byref(warm), 1, ctypes.byref(t)) == 0

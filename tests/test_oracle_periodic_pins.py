@@ -129,7 +129,7 @@ def _oracle_langmuir(u, nx, ppc, periods, amplitude):
         run.step(1)
         ts.append((n + 1) * cfg["dt"])
         ys.append(run.monitor())
-    return workloads.zero_crossing_frequency(np.array(ts), np.array(ys)), w_ref
+    return workloads.fit_frequency(np.array(ts), np.array(ys), w_ref), w_ref
 
 
 def test_oracle_langmuir_pic_matches_bohm_gross():
