@@ -147,6 +147,8 @@ def lib():
             "orc_acc_e": (_D, [_VP]),
             "orc_acc_flux": (_D, [_VP, _I32]),
             "orc_monitor": (_D, [_VP]),
+            "orc_set_speed_limit": (ctypes.c_int, [_VP, _D, _D]),
+            "orc_run_weight": (_D, [_VP, _I32]),
             "orc_absorbed_total": (_I64, [_VP, _I32]),
             "orc_injected_total": (_I64, [_VP, _I32]),
             "orc_get_particles": (None, [_VP, _I32, _PD, _PD, _PD, _PD]),
@@ -433,6 +435,17 @@ class Run:
     @property
     def acc_e(self) -> float:
         return lib().orc_acc_e(self._h)
+
+    def set_speed_limit(self, u: float, dt: float):
+        """Raise the speed limit mid-run: resample the g-particles so that
+        f = beta g is kept at the weight of a fresh load at u, set dt,
+        recompute the fields."""
+        if lib().orc_set_speed_limit(self._h, float(u), float(dt)) != 0:
+            raise ValueError("speed limit may only rise, dt must be positive")
+        self.cfg["u"], self.cfg["dt"] = float(u), float(dt)
+
+    def weight(self, s: int) -> float:
+        return lib().orc_run_weight(self._h, s)
 
     def monitor(self) -> float:
         """The monitored value: Phi_w (sheath), phi(L/2) (plates), the

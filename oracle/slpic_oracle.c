@@ -986,6 +986,63 @@ static double orc_monitor_potential(const orc_run* r) {
 }
 
 double orc_monitor(const orc_run* r) { return orc_monitor_potential(r); }
+double orc_run_weight(const orc_run* r, int32_t s) { return r->w[s]; }
+
+/* A new speed limit mid-run (the paper allows the limit to vary in time, to
+ * adjust the approximation during a simulation).  The physical distribution
+ * f = beta g is kept: the species weight becomes that of a fresh load at
+ * the new limit, w' = dx Z(u')/ppc, and each live g-particle of velocity v,
+ * in slot order, is replaced by m copies, m = floor(p) + [U < p - floor(p)]
+ * with p = (beta_u(|v|) w) / (beta_u'(|v|) w'), so that the expected
+ * beta' w' g' equals beta w g at every velocity (a raise only: then beta'
+ * >= beta and p <= w/w', at most 255 copies).  U is the first draw of the
+ * particle's own stream (purpose 6, its slot index, the current step).
+ * Then dt becomes dt' and the charge and fields are recomputed. */
+int orc_set_speed_limit(orc_run* r, double u_new, double dt_new) {
+    orc_config nc = r->cfg;
+    if (!(u_new >= r->cfg.u) || !(dt_new > 0.0)) return -1;
+    nc.u = u_new;
+    nc.dt = dt_new;
+    for (int s = 0; s < r->cfg.nspecies; ++s) {
+        double w_old = r->w[s], w_new = orc_weight(&nc, s);
+        int64_t n = r->n[s], total = 0;
+        int32_t* m = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+        for (int64_t i = 0; i < n; ++i) {
+            if (r->x[s][i] < 0.0) continue;
+            double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+            double s2 = norm2(v);
+            double p = (beta_of_s2(r->cfg.beta_kind, r->cfg.u, s2) * w_old) /
+                       (beta_of_s2(r->cfg.beta_kind, u_new, s2) * w_new);
+            orc_stream st;
+            stream_init(&st, &r->cfg, (uint32_t)i, (uint32_t)r->step, ORC_PURPOSE_LIMIT, s);
+            double fl = floor(p);
+            int64_t c = (int64_t)fl + (stream_next(&st) < p - fl ? 1 : 0);
+            m[i] = (int32_t)(c < 255 ? c : 255);
+            total += m[i];
+        }
+        double* nxs = (double*)malloc(sizeof(double) * (size_t)(total + 1));
+        double* nvx = (double*)malloc(sizeof(double) * (size_t)(total + 1));
+        double* nvy = (double*)malloc(sizeof(double) * (size_t)(total + 1));
+        double* nvz = (double*)malloc(sizeof(double) * (size_t)(total + 1));
+        int64_t k = 0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int32_t c = 0; c < m[i]; ++c, ++k) {
+                nxs[k] = r->x[s][i]; nvx[k] = r->vx[s][i]; nvy[k] = r->vy[s][i]; nvz[k] = r->vz[s][i];
+            }
+        ensure_capacity(r, s, total + 1);
+        memcpy(r->x[s], nxs, sizeof(double) * (size_t)total);
+        memcpy(r->vx[s], nvx, sizeof(double) * (size_t)total);
+        memcpy(r->vy[s], nvy, sizeof(double) * (size_t)total);
+        memcpy(r->vz[s], nvz, sizeof(double) * (size_t)total);
+        r->n[s] = total;
+        free(nxs); free(nvx); free(nvy); free(nvz); free(m);
+        r->w[s] = w_new;
+        r->qw[s] = r->cfg.species[s].charge * w_new;
+    }
+    r->cfg = nc;
+    orc_refresh_fields(r);
+    return 0;
+}
 
 /* One step of Eq. (A2a-d). */
 void orc_step(orc_run* r, int32_t nsteps) {

@@ -31,7 +31,7 @@ extern "C" {
 enum { ORC_BETA_STEP = 0, ORC_BETA_SMOOTH = 1 };
 enum { ORC_KICK_EXACT = 0, ORC_KICK_MMP = 1 };
 enum { ORC_PURPOSE_LOAD = 1, ORC_PURPOSE_INJECT = 2, ORC_PURPOSE_WARM_COUNT = 3, ORC_PURPOSE_WARM = 4,
-       ORC_PURPOSE_WALL = 5 };
+       ORC_PURPOSE_WALL = 5, ORC_PURPOSE_LIMIT = 6 };
 /* Geometry: the sheath (symmetry plane at x = 0, grounded absorbing wall at
  * x = L, volume pair source), the two conducting plates of Sec. IV
  * (phi(0) = 0, phi(L) = bias, both absorbing, half-Maxwellian flux injected
@@ -155,6 +155,13 @@ int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const d
 void orc_set_counters(orc_run* r, int64_t step, double acc_e);
 /* Plates: the fractional wall injection carried over, per species. */
 double orc_acc_flux(const orc_run* r, int32_t s);
+/* A higher speed limit mid-run (u_new >= the current u; dt_new > 0): f =
+ * beta g is kept by resampling the g-particles at the weight of a fresh
+ * load at u_new; then the fields are recomputed.  Returns 0, or -1 for an
+ * invalid argument. */
+int orc_set_speed_limit(orc_run* r, double u_new, double dt_new);
+/* The current macroparticle weight of species s. */
+double orc_run_weight(const orc_run* r, int32_t s);
 /* The monitored value after the last field solve: Phi_w (sheath), phi at
  * node nx/2 (plates), the fundamental sine amplitude of E (periodic). */
 double orc_monitor(const orc_run* r);
