@@ -577,6 +577,59 @@ def run_plates(args, ppc: int = 9000, runs: int = 1) -> dict:
     return out
 
 
+def run_langmuir(args, nx: int = 128, ppc: int = 4000, seeds: int = 8, steps: int = 700) -> dict:
+    """The speed-limited plasma frequency (plasma-oscillation section): a
+    periodic box per (u, seed), u/v_te in {0.1, 0.25, 0.5, 1, 2, inf}, all in
+    one FP32 context (48 runs, 49M particles), electrons displaced by a 0.3 %
+    sine; the seed-averaged amplitude of E's fundamental mode from the device
+    history, fitted frequency against the root of the speed-limited
+    dispersion relation and its long-wavelength limit
+    omega_p <(beta v_x)^2>^(1/2)/v_t (the oracle's quadratures)."""
+    import torch
+    import numpy as np
+    import oracle
+    import workloads
+    from paper_1511_08225_amd import slpic
+    us = [0.1, 0.25, 0.5, 1.0, 2.0, math.inf]
+    cfgs = []
+    for r, u in enumerate(us):
+        for sd in range(seeds):
+            cfgs.append(dict(workloads.langmuir_box(u, nx=nx, ppc=ppc, seed=40 + 100 * sd + r, sort_every=16),
+                             run=len(cfgs)))
+    with torch.cuda.stream(torch.cuda.Stream()):
+        sim = slpic.Sim(cfgs, precision="f32", sort_every=16, graph_steps=16)
+        for r in range(len(cfgs)):
+            xe, vxe, vpe = sim.export_particles(r, 0)
+            sim.import_particles(r, 0, workloads.langmuir_displacement(xe, nx, 0.003), vxe, vpe)
+        sim.refresh_fields()
+        torch.cuda.synchronize()
+        p0 = sim.pushed_total()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        pushes = sim.pushed_total() - p0
+        hist = np.array([sim.wall_history(r)[-steps:] for r in range(len(cfgs))])
+        flags = [s["error_flags"] for s in sim.status()]
+        sim.close()
+    k = 2 * math.pi / (nx * 0.5)
+    rows = []
+    for r, u in enumerate(us):
+        dt = cfgs[r * seeds]["dt"]
+        t = dt * np.arange(1, steps + 1)
+        root = oracle.slpic_dispersion("step", 8.0 if math.isinf(u) else u, k)
+        w = workloads.fit_frequency(t, hist[r * seeds:(r + 1) * seeds].mean(axis=0), root)
+        rows.append({"u_over_vte": None if math.isinf(u) else u, "dt": dt, "omega_measured": w,
+                     "omega_dispersion_root": root,
+                     "omega_long_wavelength": math.sqrt(oracle.slpic_plasma_freq2("step", u)),
+                     "rel_err": w / root - 1.0, "omega_dt": w * dt})
+    return {"metric": "speed-limited plasma frequency omega_s/omega_p (periodic box, fundamental mode)",
+            "rows": rows, "k_lambda_D": k, "runs": len(cfgs), "particles": 2 * nx * ppc * len(cfgs), "steps": steps,
+            "wall_s": wall, "pushes_per_s": pushes / wall, "error_flags": flags, "dtype": "f32",
+            "config": {"workload": f"periodic box, {nx} cells of 0.5 Debye lengths, {ppc} g-particles per cell per "
+                                   f"species, argon, Te/Ti = 20, {seeds} seeds per u, 0.3 % density perturbation"}}
+
+
 def launch_params(cfg, args) -> dict:
     """Push chunk, workgroup size, sort period and bucket: from the autotuner
     (cached per workload signature) unless given on the command line."""
@@ -653,6 +706,8 @@ def main() -> int:
     ap.add_argument("--only-wave", action="store_true", help="the wave-particle test-particle line alone, and exit")
     ap.add_argument("--no-wave", action="store_true", help="leave out the wave-particle measurement")
     ap.add_argument("--only-plates", action="store_true", help="the two-plate PIC vs SLPIC experiment alone, and exit")
+    ap.add_argument("--only-langmuir", action="store_true", help="the speed-limited plasma frequency alone, and exit")
+    ap.add_argument("--no-langmuir", action="store_true", help="leave out the speed-limited plasma frequency")
     ap.add_argument("--no-plates", action="store_true", help="leave out the two-plate PIC vs SLPIC experiment")
     ap.add_argument("--plates-ppc", type=int, default=9000, help="g-particles per cell at n0 in the plates experiment")
     ap.add_argument("--plates-runs", type=int, default=1, help="seeds per context in the plates experiment")
@@ -690,6 +745,9 @@ def main() -> int:
         return 0
     if args.only_plates:
         print(json.dumps(run_plates(args, args.plates_ppc, args.plates_runs)), flush=True)
+        return 0
+    if args.only_langmuir:
+        print(json.dumps(run_langmuir(args)), flush=True)
         return 0
 
     import workloads
@@ -758,6 +816,8 @@ def main() -> int:
         line["wave_test"] = run_wave(args)
     if not args.no_plates:
         line["plates_sheath"] = run_plates(args, args.plates_ppc, args.plates_runs)
+    if not args.no_langmuir:
+        line["plasma_frequency"] = run_langmuir(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -232,6 +232,23 @@ int slpic_import_particles(void* ctx, int32_t run, int32_t species, const double
  * fractional electron-injection accumulator of one run. */
 int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e);
 
+/* Sync.  Raise the speed limit of one run mid-run to u (>= its current
+ * limit; +INFINITY turns it into standard PIC) with time step dt from the
+ * next step on (the paper lets the limit vary in time, to adjust the
+ * approximation during a simulation).  The physical distribution f = beta g
+ * is kept: the species weights become those of a fresh load at u (w' = dx
+ * Z(u)/ppc), and each live g-particle of the run, of velocity v, is
+ * replaced by m copies, m = floor(p) + [U < p - floor(p)], p = (beta_old(|v|)
+ * w) / (beta_u(|v|) w') <= w/w' (at most 255), U the first draw of its own
+ * Philox stream (purpose 6, its slot, the step count); the copies keep the
+ * slot order with dead slots dropped, in every run of the context (the
+ * others keep each live particle once).  Then the charge and fields are
+ * recomputed.  The last sort permutation is overwritten.  Copies beyond the
+ * capacity are dropped with SLPIC_FLAG_CAPACITY.  SLPIC_EINVAL for u below
+ * the current limit, dt <= 0, a plates run whose wall flux per step would
+ * grow, or a context too large for the int32 scan of copy counts. */
+int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* stream);
+
 /* Sync.  Sets the fractional wall-injection accumulators of one run of the
  * plates geometry (h_acc: 2 doubles in [0, 1), electrons then ions). */
 int slpic_set_flux_counters(void* ctx, int32_t run, const double* h_acc);

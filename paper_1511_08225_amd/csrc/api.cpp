@@ -211,6 +211,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             } else {
                 step_mixture(R.ut[s], R.Ps[s], R.Pf[s]);
             }
+            R.ppc[s] = sp.ppc;
             R.nload[s] = plates ? 0 : (int64_t)c.nx * sp.ppc;  // plates: the box starts empty
             // plates: the one-sided flux v_t / sqrt(2 pi) of unit density, in g-particles per step
             R.wall_flux[s] = plates ? R.vt[s] / std::sqrt(2.0 * M_PI) * c.dt / R.w[s] : 0.0;
@@ -307,7 +308,9 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.counts = take(sizeof(int2) * kMaxSpecies * kCountSlots * nruns);
     L.push_err = take(sizeof(int) * nruns);
     L.Macc = take(sizeof(double) * 7 * P.total_nodes);
-    L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
+    // block totals of the scans: the sort histogram, or one count per slot
+    // (speed-limit resampling)
+    L.btot = take(sizeof(long long) * (scan_blocks(std::max<int64_t>(P.hist_entries, P.total_slots)) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
     L.injb = take(sizeof(int4) * P.injb.size());
     L.total = o;
@@ -784,6 +787,64 @@ int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e) {
     if (int rc = copy_h2d(&c->a.state[run].step, &step, sizeof step)) return rc;
     if (int rc = copy_h2d(&c->a.state[run].acc_e, &acc_e, sizeof acc_e)) return rc;
     c->steps_done = step;
+    return SLPIC_OK;
+}
+
+int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c || run < 0 || run >= c->P.nruns || !(dt > 0.0) || !(u > 0.0)) return SLPIC_EINVAL;
+    RunInfo Rn = c->P.runs[run];
+    const RunInfo& R = c->P.runs[run];
+    if (!(u >= R.u)) return SLPIC_EINVAL;  // the limit may only rise (then p <= w/w')
+    Rn.uinf = std::isinf(u) ? 1 : 0;
+    Rn.u = u;
+    Rn.u2 = u * u;
+    Rn.dt = dt;
+    Rn.dtdx = dt / R.dx;
+    LimitArgs L{};
+    L.run = run;
+    L.uinf = Rn.uinf;
+    L.u = u;
+    L.u2 = Rn.u2;
+    double most = 1.0;
+    for (int s = 0; s < 2; ++s) {
+        Rn.ut[s] = u / R.vt[s];
+        Rn.w[s] = R.dx * mean_inv_beta(R.beta_kind, Rn.ut[s]) / (double)R.ppc[s];
+        Rn.qw[s] = R.qw[s] / R.w[s] * Rn.w[s];  // the species charge times the new weight
+        if (Rn.uinf) {
+            Rn.Ps[s] = 1.0;
+            Rn.Pf[s] = 0.0;
+        } else {
+            step_mixture(Rn.ut[s], Rn.Ps[s], Rn.Pf[s]);
+        }
+        if (R.geom == kGeomPlates) {
+            Rn.wall_flux[s] = R.vt[s] / std::sqrt(2.0 * M_PI) * dt / Rn.w[s];
+            // the injection workgroups were planned for the old flux per step
+            if (Rn.wall_flux[s] > R.wall_flux[s]) return SLPIC_EINVAL;
+        }
+        L.w[s] = Rn.w[s];
+        most = std::max(most, std::ceil(R.w[s] / Rn.w[s]));
+    }
+    Rn.inj_ratio = Rn.w[1] / Rn.w[0];
+    // the scan of copy counts runs in int32 over every slot
+    if ((double)c->P.total_slots * std::min(most, (double)kLimitMaxCopies) >= 2147483647.0) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipDeviceSynchronize());
+    const int nch = (int)c->P.chunks.size();
+    if (prec(c) == SLPIC_F32) launch_limit_f32(c->a, L, nch, 0, s);
+    else launch_limit_f64(c->a, L, nch, 0, s);
+    launch_scan_ints(c->a.perm, c->P.total_slots, c->btot, s);
+    if (prec(c) == SLPIC_F32) launch_limit_f32(c->a, L, nch, 1, s);
+    else launch_limit_f64(c->a, L, nch, 1, s);
+    launch_limit_finish(c->a, c->P.nruns, c->P.total_slots, c->btot, s);
+    HIP_TRY(hipGetLastError());
+    // the new run parameters, once the resampling (which reads the old ones) is done
+    c->P.runs[run] = Rn;
+    if (int rc = copy_h2d((void*)(c->a.runs + run), &Rn, sizeof(RunInfo))) return rc;
+    l_push(c, false, s);
+    launch_field(c->a, c->P.nruns, 0, c->field_lds, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
     return SLPIC_OK;
 }
 

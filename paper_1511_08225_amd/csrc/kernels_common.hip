@@ -108,6 +108,25 @@ __global__ void k_sort_finish(KArgs a, int nruns, int64_t hist_entries, const lo
     }
 }
 
+// After a speed-limit resampling: every (run, species) segment's new count
+// from the scanned copy counts (the next segment's first entry, or the
+// grand total), capped at the capacity with the sticky flag, and the
+// particle buffers swapped.
+__global__ void k_limit_finish(KArgs a, int nruns, int64_t total_slots, const long long* btot, int nblk) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) *a.cur ^= 1;
+    if (r >= nruns) return;
+    const RunInfo& R = a.runs[r];
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        const int64_t e = R.poff[s] + R.cap[s];
+        const long long base = a.perm[R.poff[s]];
+        const long long end = e < total_slots ? (long long)a.perm[e] : btot[nblk];
+        const long long n = end - base;
+        if (n > R.cap[s]) a.state[r].error |= 1;
+        a.state[r].nslots[s] = n < R.cap[s] ? n : R.cap[s];
+    }
+}
+
 __global__ void k_zero(double* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0;
@@ -178,6 +197,10 @@ void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const l
                         hipStream_t s) {
     hipLaunchKernelGGL(k_sort_finish, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns, hist_entries,
                        btot, scan_blocks(hist_entries));
+}
+void launch_limit_finish(const KArgs& a, int nruns, int64_t total_slots, const long long* btot, hipStream_t s) {
+    hipLaunchKernelGGL(k_limit_finish, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns, total_slots, btot,
+                       scan_blocks(total_slots));
 }
 void launch_zero(double* p, int64_t n, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;

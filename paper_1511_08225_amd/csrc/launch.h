@@ -17,6 +17,7 @@ namespace slpic {
                                    hipStream_t s);                                                     \
     void launch_source_field_##sfx(const KArgs& a, int nruns, size_t lds, hipStream_t s);              \
     void launch_wall_inject_##sfx(const KArgs& a, hipStream_t s);                                      \
+    void launch_limit_##sfx(const KArgs& a, const LimitArgs& L, int nchunks, int scatter, hipStream_t s); \
     void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \
                               double* out, int per_run, hipStream_t s);                                \
     void launch_sort_hist_##sfx(const KArgs& a, int ntiles, int block, size_t lds, hipStream_t s);     \
@@ -36,6 +37,7 @@ void launch_scan_ints(int* h, int64_t n, long long* btot, hipStream_t s);
 void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const long long* btot,
                         hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);
+void launch_limit_finish(const KArgs& a, int nruns, int64_t total_slots, const long long* btot, hipStream_t s);
 void launch_moments_finish(const KArgs& a, int run, double* out, hipStream_t s);
 void launch_moments_window(const KArgs& a, int run, double* out, int reset, hipStream_t s);
 void launch_moments_sample_finish(const KArgs& a, int run0, int nruns, hipStream_t s);

@@ -13,6 +13,8 @@ constexpr int kPurposeInject = 2;
 constexpr int kPurposeWarmCount = 3;  // warm load: rounding of a cell's count
 constexpr int kPurposeWarm = 4;       // warm load: one particle
 constexpr int kPurposeWall = 5;       // plates: a particle entering through x = L
+constexpr int kPurposeLimit = 6;      // a new speed limit: the resampling draw of a particle
+constexpr int kLimitMaxCopies = 255;  // copies of one g-particle when the speed limit rises
 constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
 constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
 constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
@@ -51,6 +53,14 @@ struct RunInfo {
     double steady_tol;           // relative spread of three window means that counts as steady
     double bias;                 // plates: phi(L)
     double wall_flux[kMaxSpecies];  // plates: g-particles entering per step, per species
+    int32_t ppc[kMaxSpecies];    // g-particles per cell at unit density (sets the weight)
+};
+
+// A new (higher) speed limit for one run: the new limit and the new weights.
+struct LimitArgs {
+    int32_t run, uinf;
+    double u, u2;
+    double w[kMaxSpecies];
 };
 
 // Mutable per-run state, updated on the device.

@@ -137,6 +137,7 @@ def lib():
             "slpic_set_counters": (ctypes.c_int, [_P, i32, i64, ctypes.c_double]),
             "slpic_set_flux_counters": (ctypes.c_int, [_P, i32, _PD]),
             "slpic_set_sampling": (ctypes.c_int, [_P, i32]),
+            "slpic_set_speed_limit": (ctypes.c_int, [_P, i32, ctypes.c_double, ctypes.c_double, _P]),
             "slpic_refresh_fields": (ctypes.c_int, [_P, _P]),
             "slpic_export_grid": (ctypes.c_int, [_P, i32, _PD, _PD, _PD]),
             "slpic_sort_now": (ctypes.c_int, [_P, _P]),
@@ -332,6 +333,13 @@ class Sim:
 
     def set_counters(self, run: int, step: int, acc_e: float):
         _check(lib().slpic_set_counters(self._ctx, run, int(step), float(acc_e)), "slpic_set_counters")
+
+    def set_speed_limit(self, run: int, u: float, dt: float):
+        """Raise run's speed limit to u with time step dt (f = beta g kept by
+        resampling the g-particles at the weight of a fresh load at u)."""
+        _check(lib().slpic_set_speed_limit(self._ctx, int(run), float(u), float(dt), self._stream()),
+               "slpic_set_speed_limit")
+        self.configs[run]["u"], self.configs[run]["dt"] = float(u), float(dt)
 
     def set_flux_counters(self, run: int, acc):
         a = np.ascontiguousarray(acc, dtype=np.float64)
