@@ -328,6 +328,9 @@ struct Context {
     long long* btot = nullptr;
     int64_t steps_done = 0;
     size_t push_lds = 0, field_lds = 0, source_field_lds = 0, sort_lds = 0, moments_lds = 0;
+    // threads of the per-run source + field workgroup (fewer waves helped the
+    // 100-cell plates step by ~5 % but slowed the 2048-cell sheath by 10-20 %)
+    int field_threads = kFieldThreads;
     hipGraphExec_t gexec = nullptr;
     int graph_len = 0;
     bool prof = false;
@@ -368,8 +371,8 @@ void l_wall_inject(Context* c, hipStream_t s) {
     else launch_wall_inject_f64(c->a, s);
 }
 void l_source_field(Context* c, hipStream_t s) {
-    if (prec(c) == SLPIC_F32) launch_source_field_f32(c->a, c->P.nruns, c->source_field_lds, s);
-    else launch_source_field_f64(c->a, c->P.nruns, c->source_field_lds, s);
+    if (prec(c) == SLPIC_F32) launch_source_field_f32(c->a, c->P.nruns, c->field_threads, c->source_field_lds, s);
+    else launch_source_field_f64(c->a, c->P.nruns, c->field_threads, c->source_field_lds, s);
 }
 
 // timed launch wrapper: class k in {0 push, 1 source (inside the field launch), 2 field, 3 sort}
@@ -537,6 +540,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     c->field_lds = (size_t)c->P.max_nodes * 8 + 32 * 8;
     c->sort_lds = (size_t)4 * c->P.max_nkeys * sizeof(int);
     c->source_field_lds = c->field_lds + (size_t)2 * c->P.max_src * 8;
+
     c->moments_lds = (size_t)3 * c->P.max_nodes * 8;
     if (c->push_lds > 65536 || c->sort_lds > 65536 || c->moments_lds > 65536 || c->source_field_lds > 65536) {
         delete c;

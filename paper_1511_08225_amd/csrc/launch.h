@@ -15,7 +15,7 @@ namespace slpic {
     void launch_velocity_map_##sfx(int beta_kind, double u, double dt, int64_t n, const void* vx,      \
                                    const void* c2, const void* acc, void* out, int* iters,             \
                                    hipStream_t s);                                                     \
-    void launch_source_field_##sfx(const KArgs& a, int nruns, size_t lds, hipStream_t s);              \
+    void launch_source_field_##sfx(const KArgs& a, int nruns, int threads, size_t lds, hipStream_t s); \
     void launch_wall_inject_##sfx(const KArgs& a, hipStream_t s);                                      \
     void launch_limit_##sfx(const KArgs& a, const LimitArgs& L, int nchunks, int scatter, hipStream_t s); \
     void launch_moments_##sfx(const KArgs& a, int chunk0, int nchunks, int block, size_t lds,          \

@@ -18,6 +18,8 @@ constexpr int kLimitMaxCopies = 255;  // copies of one g-particle when the speed
 constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
 constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
 constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
+constexpr int kFieldPer = 16;         // field solve: nodes per thread kept in registers
+constexpr int kFieldThreads = 1024;   // field solve: threads of the per-run workgroup, at most
 constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers
 constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the injection LDS window
 constexpr int kInjectThreads = 128;     // plates: particles per wall-injection workgroup
