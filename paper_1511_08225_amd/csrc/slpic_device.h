@@ -331,7 +331,11 @@ __device__ __forceinline__ T kick1d(T vx, T c2, T a, T dt, T u, T u2, bool uinf,
     } else if (c2 < u2) {
         // Eq. (11b): fast toward the band, slow inside |p| <= ps, fast beyond
         const T ps = Fm<T>::sqrt(u2 - c2);
-        if (p0 < -ps) {
+        // reaching the band from p0 < -ps takes the speed integral
+        // G(-ps) - G(p0) >= (p0^2 - ps^2)/2 (the speed is at least |p|): when
+        // that bound already exceeds the step's A u dt, the two G evaluations
+        // (two logarithms) are skipped
+        if (p0 < -ps && T(0.5) * (p0 * p0 - ps * ps) < A * u * dt) {
             const T c = Fm<T>::sqrt(c2);
             const T Kneed = G_of(c2, c, -ps, u) - G_of(c2, c, p0, Fm<T>::sqrt(p0 * p0 + c2));
             if (Kneed < A * u * dt) {  // reaches the band
