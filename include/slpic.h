@@ -249,6 +249,16 @@ int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e);
  * grow, or a context too large for the int32 scan of copy counts. */
 int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* stream);
 
+/* Sync.  With tuning.retire_steady, takes every run that has retired
+ * (frozen at its steady step) and is not yet pruned out of the push and sort
+ * work: its particles are copied into both particle buffers (the sort no
+ * longer moves them), the push launch and captured graphs cover only the
+ * remaining runs' chunks, and the sort keeps a pruned run's counts.  Its
+ * state, moments, exports and refresh stay available.  *h_pruned (may be
+ * NULL) receives the number of pruned runs.  Retired runs cost no push or
+ * sort work only once pruned; call it at the cadence the status is polled. */
+int slpic_prune_retired(void* ctx, int32_t* h_pruned, void* stream);
+
 /* Sync.  Sets the fractional wall-injection accumulators of one run of the
  * plates geometry (h_acc: 2 doubles in [0, 1), electrons then ions). */
 int slpic_set_flux_counters(void* ctx, int32_t run, const double* h_acc);

@@ -124,7 +124,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
-        totals, counts, push_err, Macc, btot, history, injb, total;
+        totals, counts, push_err, Macc, btot, history, injb, active, total;
 };
 
 struct Plan {
@@ -313,6 +313,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.btot = take(sizeof(long long) * (scan_blocks(std::max<int64_t>(P.hist_entries, P.total_slots)) + 1));
     L.history = take(sizeof(double) * kHistoryLen * nruns);
     L.injb = take(sizeof(int4) * P.injb.size());
+    L.active = take(sizeof(Chunk) * P.chunks.size());  // the push's chunks: runs not pruned
     L.total = o;
     return SLPIC_OK;
 }
@@ -338,6 +339,8 @@ struct Context {
     std::vector<EventPair> ev[4];
     size_t ev_used[4] = {0, 0, 0, 0};
     int sample_every = 0;  // in-step moment sampling period (0: off)
+    Chunk* active = nullptr;  // device: the chunks of runs not pruned (the push's work)
+    int n_active = 0;
     ~Context() {
         if (gexec) hipGraphExecDestroy(gexec);
         for (auto& v : ev)
@@ -359,12 +362,16 @@ void l_load(Context* c, hipStream_t s) {
     if (prec(c) == SLPIC_F32) launch_load_f32(c->a, (int)c->P.chunks.size(), 256, s);
     else launch_load_f64(c->a, (int)c->P.chunks.size(), 256, s);
 }
+// A pushing launch covers the chunks of the runs not pruned; a deposit-only
+// launch (refresh) every chunk.
 void l_push(Context* c, bool push, hipStream_t s) {
     const int per = c->P.tun.chunk / 64;
+    const Chunk* ch = push ? c->active : c->a.chunks;
+    const int n = push ? c->n_active : (int)c->P.chunks.size();
     if (prec(c) == SLPIC_F32)
-        launch_push_f32(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, s);
+        launch_push_f32(push, per, c->a, ch, n, c->P.tun.block, s);
     else
-        launch_push_f64(push, per, c->a, (int)c->P.chunks.size(), c->P.tun.block, s);
+        launch_push_f64(push, per, c->a, ch, n, c->P.tun.block, s);
 }
 void l_wall_inject(Context* c, hipStream_t s) {
     if (prec(c) == SLPIC_F32) launch_wall_inject_f32(c->a, s);
@@ -460,6 +467,24 @@ int build_graph(Context* c, hipStream_t s) {
 // if event records cannot be captured; the caller then launches directly.
 Context* ctx_of(void* p) { return static_cast<Context*>(p); }
 
+// Both particle buffers of (run) hold the current one's slots.
+int mirror_run(Context* c, int run, hipStream_t s) {
+    const RunInfo& R = c->P.runs[run];
+    int b = 0;
+    HIP_TRY(hipMemcpy(&b, c->a.cur, sizeof(int), hipMemcpyDeviceToHost));
+    const size_t esz = prec(c) == SLPIC_F32 ? 4 : 8;
+    for (int sp = 0; sp < 2; ++sp) {
+        const size_t off = (size_t)R.poff[sp] * esz, bytes = (size_t)R.cap[sp] * esz;
+        HIP_TRY(hipMemcpyAsync((char*)c->a.bufs.x[b ^ 1] + off, (char*)c->a.bufs.x[b] + off, bytes,
+                               hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync((char*)c->a.bufs.vx[b ^ 1] + off, (char*)c->a.bufs.vx[b] + off, bytes,
+                               hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync((char*)c->a.bufs.vp2[b ^ 1] + off, (char*)c->a.bufs.vp2[b] + off, bytes,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    return SLPIC_OK;
+}
+
 // The synchronous copies of the "sync" calls wait for the whole device
 // first: work enqueued on a non-blocking stream is not ordered with the
 // default stream that hipMemcpy uses.
@@ -534,6 +559,8 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.history = (double*)(w + L.history);
     a.injb = (const int4*)(w + L.injb);
     a.ninjb = (int32_t)c->P.injb.size();
+    c->active = (Chunk*)(w + L.active);
+    c->n_active = (int)c->P.chunks.size();
     c->btot = (long long*)(w + L.btot);
     const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
     c->push_lds = (size_t)c->P.max_nodes * (8 + tsz) + 16;
@@ -559,6 +586,8 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     INIT_TRY(hipMemcpyAsync((void*)a.chunks, c->P.chunks.data(), sizeof(Chunk) * c->P.chunks.size(),
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     INIT_TRY(hipMemcpyAsync((void*)a.tiles, c->P.tiles.data(), sizeof(Tile) * c->P.tiles.size(),
+                            hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
+    INIT_TRY(hipMemcpyAsync((void*)c->active, c->P.chunks.data(), sizeof(Chunk) * c->P.chunks.size(),
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     if (!c->P.injb.empty())
         INIT_TRY(hipMemcpyAsync((void*)a.injb, c->P.injb.data(), sizeof(int4) * c->P.injb.size(),
@@ -781,7 +810,12 @@ int slpic_import_particles(void* ctx, int32_t run, int32_t species, const double
         if (int rc = copy_h2d((double*)c->a.bufs.vp2[b] + po, h_vperp2, 8 * n)) return rc;
     }
     int64_t nn = n;
-    return copy_h2d(&c->a.state[run].nslots[species], &nn, sizeof nn);
+    if (int rc = copy_h2d(&c->a.state[run].nslots[species], &nn, sizeof nn)) return rc;
+    if (R.pruned) {  // not sorted again: both buffers hold the new slots
+        if (int rc = mirror_run(c, run, nullptr)) return rc;
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    return SLPIC_OK;
 }
 
 int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e) {
@@ -842,6 +876,10 @@ int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* str
     else launch_limit_f64(c->a, L, nch, 1, s);
     launch_limit_finish(c->a, c->P.nruns, c->P.total_slots, c->btot, s);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int r = 0; r < c->P.nruns; ++r)  // pruned runs are not sorted: both buffers keep them
+        if (c->P.runs[r].pruned)
+            if (int rc = mirror_run(c, r, s)) return rc;
     // the new run parameters, once the resampling (which reads the old ones) is done
     c->P.runs[run] = Rn;
     if (int rc = copy_h2d((void*)(c->a.runs + run), &Rn, sizeof(RunInfo))) return rc;
@@ -849,6 +887,43 @@ int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* str
     launch_field(c->a, c->P.nruns, 0, c->field_lds, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
+    return SLPIC_OK;
+}
+
+
+int slpic_prune_retired(void* ctx, int32_t* h_pruned, void* stream) {
+    Context* c = ctx_of(ctx);
+    if (!c) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<RunState> st(c->P.nruns);
+    if (int rc = copy_d2h(st.data(), c->a.state, sizeof(RunState) * c->P.nruns)) return rc;
+    int newly = 0, total = 0;
+    for (int r = 0; r < c->P.nruns; ++r) {
+        RunInfo& R = c->P.runs[r];
+        if (!R.pruned && retired(R, st[r])) {
+            if (int rc = mirror_run(c, r, s)) return rc;
+            R.pruned = 1;
+            HIP_TRY(hipMemcpyAsync((void*)(c->a.runs + r), &R, sizeof(RunInfo), hipMemcpyHostToDevice, s));
+            ++newly;
+        }
+        total += R.pruned;
+    }
+    if (newly) {
+        std::vector<Chunk> act;
+        act.reserve(c->P.chunks.size());
+        for (const Chunk& ch : c->P.chunks)
+            if (!c->P.runs[ch.run].pruned) act.push_back(ch);
+        if (!act.empty())
+            HIP_TRY(hipMemcpyAsync(c->active, act.data(), sizeof(Chunk) * act.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        c->n_active = (int)act.size();
+        if (c->gexec) {  // captured with the old push grid
+            hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+    }
+    if (h_pruned) *h_pruned = total;
     return SLPIC_OK;
 }
 

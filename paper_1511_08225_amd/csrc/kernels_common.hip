@@ -100,6 +100,7 @@ __global__ void k_sort_finish(KArgs a, int nruns, int64_t hist_entries, const lo
     if (r == 0) *a.cur ^= 1;
     if (r >= nruns) return;
     const RunInfo& R = a.runs[r];
+    if (R.pruned) return;  // not sorted: its counts stand
     for (int s = 0; s < kMaxSpecies; ++s) {
         const int64_t e = R.hoff[s] + (int64_t)R.nkeys * R.ntiles[s];
         const long long base = a.hist[R.hoff[s]];

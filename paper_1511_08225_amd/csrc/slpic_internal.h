@@ -56,6 +56,9 @@ struct RunInfo {
     double bias;                 // plates: phi(L)
     double wall_flux[kMaxSpecies];  // plates: g-particles entering per step, per species
     int32_t ppc[kMaxSpecies];    // g-particles per cell at unit density (sets the weight)
+    int32_t pruned;              // 1: retired and taken out of the push and sort work (its
+                                 // particles then sit identical in both buffers)
+    int32_t pad_p;
 };
 
 // A new (higher) speed limit for one run: the new limit and the new weights.

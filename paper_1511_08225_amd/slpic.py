@@ -138,6 +138,7 @@ def lib():
             "slpic_set_flux_counters": (ctypes.c_int, [_P, i32, _PD]),
             "slpic_set_sampling": (ctypes.c_int, [_P, i32]),
             "slpic_set_speed_limit": (ctypes.c_int, [_P, i32, ctypes.c_double, ctypes.c_double, _P]),
+            "slpic_prune_retired": (ctypes.c_int, [_P, _PI32, _P]),
             "slpic_refresh_fields": (ctypes.c_int, [_P, _P]),
             "slpic_export_grid": (ctypes.c_int, [_P, i32, _PD, _PD, _PD]),
             "slpic_sort_now": (ctypes.c_int, [_P, _P]),
@@ -333,6 +334,13 @@ class Sim:
 
     def set_counters(self, run: int, step: int, acc_e: float):
         _check(lib().slpic_set_counters(self._ctx, run, int(step), float(acc_e)), "slpic_set_counters")
+
+    def prune_retired(self) -> int:
+        """Take retired runs out of the push and sort work; returns how many
+        runs are pruned."""
+        n = ctypes.c_int32(0)
+        _check(lib().slpic_prune_retired(self._ctx, ctypes.byref(n), self._stream()), "slpic_prune_retired")
+        return n.value
 
     def set_speed_limit(self, run: int, u: float, dt: float):
         """Raise run's speed limit to u with time step dt (f = beta g kept by

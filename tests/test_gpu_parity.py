@@ -463,3 +463,49 @@ def test_retired_runs_freeze_at_their_steady_step(gpu_lib):
             assert rel_inf(g["Q"][s], snap[r]["Q"][s]) <= 1e-12, (r, s)
     sim.close()
     ref.close()
+
+
+def test_pruned_runs_cost_nothing_and_change_nothing(gpu_lib):
+    """slpic_prune_retired: retired runs are taken out of the push and sort
+    work (graph replay on a side stream); the pruned runs keep their frozen
+    state across sorts and buffer swaps, and the runs still active evolve
+    exactly as in a context that never prunes (FP64, same launches for them)."""
+    import torch
+    cfgs = [workloads.sheath(nx=32, ppc=40, u_over_vti=3.0, dt=5.0, seed=s, run=r, steady_window=8,
+                             steady_tol=tol, sort_every=8)
+            for r, (s, tol) in enumerate(((1, 0.5), (2, 1e-9), (3, 0.5), (4, 1e-9)))]
+    with torch.cuda.stream(torch.cuda.Stream()):
+        sim = gpu_lib.Sim(cfgs, precision="f64", sort_every=8, graph_steps=8, retire_steady=True)
+        ref = gpu_lib.Sim(cfgs, precision="f64", sort_every=8, graph_steps=8, retire_steady=True)
+        pruned = 0
+        for k in range(60):
+            sim.step(8)
+            ref.step(8)
+            pruned = sim.prune_retired()
+            if pruned == 2:
+                break
+        print_case(f"prune: {pruned} runs pruned after {8 * (k + 1)} steps")
+        assert pruned == 2
+        st0 = sim.status()
+        frozen = {r: (sim.grid(r), [_live_sorted(sim.export_particles(r, s)) for s in range(2)])
+                  for r in (0, 2)}
+        sim.step(40)  # sorts and buffer swaps with the pruned runs out of the work
+        ref.step(40)
+        st, sr = sim.status(), ref.status()
+        for r in (0, 2):
+            assert st[r]["step"] == st0[r]["step"] == st[r]["steady_step"]
+            g = sim.grid(r)
+            for key in ("Q", "phi", "E"):
+                assert np.array_equal(g[key], frozen[r][0][key]), (r, key)
+            for s in range(2):
+                assert np.array_equal(_live_sorted(sim.export_particles(r, s)), frozen[r][1][s]), (r, s)
+        for r in (1, 3):  # still active: as in the context that never prunes
+            assert st[r]["step"] == sr[r]["step"] and st[r]["nslots"] == sr[r]["nslots"]
+            g, h = sim.grid(r), ref.grid(r)
+            for s in range(2):
+                assert rel_inf(g["Q"][s], h["Q"][s]) <= 1e-12, (r, s)
+                a = _live_sorted(sim.export_particles(r, s))
+                b = _live_sorted(ref.export_particles(r, s))
+                assert np.allclose(a, b, rtol=1e-12, atol=1e-12), (r, s)
+        sim.close()
+        ref.close()
