@@ -342,11 +342,11 @@ struct Context {
     Chunk* active = nullptr;  // device: the chunks of runs not pruned (the push's work)
     int n_active = 0;
     ~Context() {
-        if (gexec) hipGraphExecDestroy(gexec);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         for (auto& v : ev)
             for (auto& e : v) {
-                if (e.a) hipEventDestroy(e.a);
-                if (e.b) hipEventDestroy(e.b);
+                if (e.a) (void)hipEventDestroy(e.a);
+                if (e.b) (void)hipEventDestroy(e.b);
             }
     }
 };
@@ -444,12 +444,12 @@ int capture_steps(Context* c, hipStream_t s, hipGraphExec_t* out) {
     for (int k = 0; k < c->P.tun.graph_steps && rc == SLPIC_OK; ++k) rc = one_step(c, k, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc != SLPIC_OK || e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         (void)hipGetLastError();
         return rc != SLPIC_OK ? rc : SLPIC_EHIP;
     }
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         *out = nullptr;
         return SLPIC_EHIP;
@@ -919,7 +919,7 @@ int slpic_prune_retired(void* ctx, int32_t* h_pruned, void* stream) {
         HIP_TRY(hipStreamSynchronize(s));
         c->n_active = (int)act.size();
         if (c->gexec) {  // captured with the old push grid
-            hipGraphExecDestroy(c->gexec);
+            (void)hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;
         }
     }
@@ -991,7 +991,7 @@ int slpic_set_sampling(void* ctx, int32_t every) {
     if (every == c->sample_every) return SLPIC_OK;
     HIP_TRY(hipDeviceSynchronize());
     if (c->gexec) {  // captured with the old step sequence
-        hipGraphExecDestroy(c->gexec);
+        (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
     }
     c->sample_every = every;

@@ -179,8 +179,8 @@ struct Ctx2 {
     ~Ctx2() {
         for (auto& v : ev)
             for (auto& e : v) {
-                if (e.a) hipEventDestroy(e.a);
-                if (e.b) hipEventDestroy(e.b);
+                if (e.a) (void)hipEventDestroy(e.a);
+                if (e.b) (void)hipEventDestroy(e.b);
             }
     }
 };
