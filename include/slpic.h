@@ -98,7 +98,7 @@ typedef struct {
 } slpic_species;
 
 typedef struct {
-    int32_t nx;            /* cells (>= 4); nodes 0..nx                         */
+    int32_t nx;            /* cells, 4..2729; nodes 0..nx                       */
     int32_t beta_kind;     /* SLPIC_BETA_STEP / SLPIC_BETA_SMOOTH               */
     double dx, dt;         /* cell size, time step                              */
     double u;              /* speed limit v0; +INFINITY reduces to standard PIC */
@@ -120,8 +120,8 @@ typedef struct {
                            /* V = Gamma/n (|V| <= 4 vt) with n dx <1/beta>/w     */
                            /* g-particles sampled as f/beta (Eq. 5)             */
     int32_t geometry;      /* SLPIC_GEOM_SHEATH (0), SLPIC_GEOM_PLATES or       */
-                           /* SLPIC_GEOM_PERIODIC; the last two need nx <= 16384 */
-                           /* and no warm_profile                               */
+                           /* SLPIC_GEOM_PERIODIC; the last two need no        */
+                           /* warm_profile                                      */
     int32_t reserved;
     double bias;           /* SLPIC_GEOM_PLATES: phi(L) in T_e/e; else unused   */
 } slpic_run_config;

@@ -165,7 +165,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     int64_t poff = 0, goff = 0, hoff = 0;
     for (int r = 0; r < nruns; ++r) {
         const slpic_run_config& c = cfg[r];
-        if (c.nx < 4 || c.nx > (1 << 20) || !(c.dx > 0) || !(c.dt > 0) || !(c.u > 0) || c.nspecies != 2 ||
+        if (c.nx < 4 || c.nx > kMaxCells || !(c.dx > 0) || !(c.dt > 0) || !(c.u > 0) || c.nspecies != 2 ||
             c.source_cells < 1 || c.source_cells > c.nx ||
             (c.beta_kind != SLPIC_BETA_STEP && c.beta_kind != SLPIC_BETA_SMOOTH))
             return SLPIC_EINVAL;
@@ -328,7 +328,7 @@ struct Context {
     unsigned char* ws = nullptr;
     long long* btot = nullptr;
     int64_t steps_done = 0;
-    size_t push_lds = 0, field_lds = 0, source_field_lds = 0, sort_lds = 0, moments_lds = 0;
+    size_t field_lds = 0, source_field_lds = 0, sort_lds = 0, moments_lds = 0;
     // threads of the per-run source + field workgroup (fewer waves helped the
     // 100-cell plates step by ~5 % but slowed the 2048-cell sheath by 10-20 %)
     int field_threads = kFieldThreads;
@@ -562,14 +562,12 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     c->active = (Chunk*)(w + L.active);
     c->n_active = (int)c->P.chunks.size();
     c->btot = (long long*)(w + L.btot);
-    const size_t tsz = c->P.tun.precision == SLPIC_F32 ? 4 : 8;
-    c->push_lds = (size_t)c->P.max_nodes * (8 + tsz) + 16;
     c->field_lds = (size_t)c->P.max_nodes * 8 + 32 * 8;
     c->sort_lds = (size_t)4 * c->P.max_nkeys * sizeof(int);
     c->source_field_lds = c->field_lds + (size_t)2 * c->P.max_src * 8;
 
     c->moments_lds = (size_t)3 * c->P.max_nodes * 8;
-    if (c->push_lds > 65536 || c->sort_lds > 65536 || c->moments_lds > 65536 || c->source_field_lds > 65536) {
+    if (c->sort_lds > 65536 || c->moments_lds > 65536 || c->source_field_lds > 65536) {
         delete c;
         return SLPIC_EINVAL;
     }

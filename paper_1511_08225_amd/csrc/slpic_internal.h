@@ -18,6 +18,9 @@ constexpr int kLimitMaxCopies = 255;  // copies of one g-particle when the speed
 constexpr int kGeomSheath = 0;        // symmetry plane at 0, grounded wall at L
 constexpr int kGeomPlates = 1;        // conducting plates at 0 and L (bias)
 constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
+// cells of a 1D run: a moments workgroup keeps 3 FP64 rows of nodes in its
+// 64 KiB of LDS (3 * 8 * 2730 bytes)
+constexpr int kMaxCells = 2729;
 constexpr int kFieldPer = 16;         // field solve: nodes per thread kept in registers
 constexpr int kFieldThreads = 1024;   // field solve: threads of the per-run workgroup, at most
 constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers

@@ -139,6 +139,11 @@ def test_plates_planning_validates_configs():
         assert L.slpic_workspace_bytes(ctypes.byref(bad), 1, ctypes.byref(t)) == 0, field
     assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(slpic.Tuning2D())) == 0
     assert "slpic_set_flux_counters" in _declared_functions()
+    # the longest run: 2729 cells
+    edge = slpic.run_config(dict(workloads.sheath(nx=2729, ppc=2, u_over_vti=3.0), sort_every=1))
+    assert L.slpic_workspace_bytes(ctypes.byref(edge), 1, ctypes.byref(t)) > 0
+    edge.nx = 2730
+    assert L.slpic_workspace_bytes(ctypes.byref(edge), 1, ctypes.byref(t)) == 0
 
 
 def test_periodic_planning_validates_configs():

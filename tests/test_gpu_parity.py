@@ -509,3 +509,37 @@ def test_pruned_runs_cost_nothing_and_change_nothing(gpu_lib):
                 assert np.allclose(a, b, rtol=1e-12, atol=1e-12), (r, s)
         sim.close()
         ref.close()
+
+
+@pytest.mark.parametrize("geometry", ["sheath", "plates", "periodic"])
+def test_field_solve_at_the_largest_grid(gpu_lib, geometry):
+    """The deposit and the one-workgroup field solve at the largest run,
+    2729 cells (3 nodes per thread; the moments workgroup's three FP64 node
+    rows bound the run length), for each geometry on 40 000 random particles
+    against the oracle (FP64)."""
+    nx = 2729
+    if geometry == "plates":
+        cfg = dict(workloads.plates_sheath(0.0158, ppc=10, sort_every=0), nx=nx)
+    elif geometry == "periodic":
+        cfg = workloads.langmuir_box(0.25, nx=nx, ppc=10, sort_every=0)
+    else:
+        cfg = workloads.sheath(nx=nx, ppc=10, u_over_vti=3.0, dt=5.0, sort_every=0)
+    rng = np.random.default_rng(91)
+    run = oracle.Run(cfg, load=False)
+    sim = gpu_lib.Sim(cfg, precision="f64", sort_every=0)
+    for s in range(2):
+        n = 20000
+        x = rng.uniform(0, nx, size=n)
+        x[rng.random(n) < 0.05] = -1.0  # dead slots
+        vx = rng.normal(size=n) * (1.0 if s == 0 else 0.01)
+        vy = rng.normal(size=n) * (1.0 if s == 0 else 0.01)
+        run.set_particles(s, x, vx, vy, np.zeros(n))
+        sim.import_particles(0, s, x, vx, vy * vy)
+    run.refresh_fields()
+    sim.refresh_fields()
+    g, o = sim.grid(0), run.grid()
+    print_case(f"field solve at {nx} cells, {geometry}")
+    for s in range(2):
+        assert rel_inf(g["Q"][s], o["Q"][s]) <= 1e-12, s
+    assert rel_inf(g["phi"], o["phi"]) <= 1e-9
+    assert rel_inf(g["E"], o["E"]) <= 1e-9
