@@ -171,9 +171,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             return SLPIC_EINVAL;
         const bool plates = c.geometry == SLPIC_GEOM_PLATES, periodic = c.geometry == SLPIC_GEOM_PERIODIC;
         if ((c.geometry != SLPIC_GEOM_SHEATH && !plates && !periodic) ||
-            (plates && (c.warm_profile || c.nx > kPlatesMaxCells || c.source_cells > kPlatesMaxSource ||
-                        !std::isfinite(c.bias))) ||
-            (periodic && (c.warm_profile || c.nx > kPlatesMaxCells)))
+            (plates && (c.warm_profile || c.source_cells > kPlatesMaxSource || !std::isfinite(c.bias))) ||
+            (periodic && c.warm_profile))
             return SLPIC_EINVAL;
         RunInfo& R = P.runs[r];
         R.nx = c.nx;

@@ -23,7 +23,6 @@ constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
 constexpr int kMaxCells = 2729;
 constexpr int kFieldPer = 16;         // field solve: nodes per thread kept in registers
 constexpr int kFieldThreads = 1024;   // field solve: threads of the per-run workgroup, at most
-constexpr int kPlatesMaxCells = 16384;  // plates: the field solve keeps every node in registers
 constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the injection LDS window
 constexpr int kInjectThreads = 128;     // plates: particles per wall-injection workgroup
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
