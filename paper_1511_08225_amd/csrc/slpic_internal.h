@@ -147,7 +147,7 @@ struct KArgs {
     int* push_err;        // [run]: error flags raised by the last push
     int32_t* perm;        // last sort's permutation (new slot -> old slot)
     double* Macc;         // moment window accumulators [run]: 7 rows of nodes at 7*goff
-    const int4* injb;     // plates: wall-injection workgroups of the push launch (run, species, first, 0)
+    const int4* injb;     // plates: wall-injection workgroups (run, species, first particle, 0)
     int32_t ninjb;        // their count (0 without plates runs)
 };
 
