@@ -138,6 +138,7 @@ struct Plan {
     std::vector<int4> injb;  // plates: wall-injection workgroups (run, species, first particle, 0)
     int64_t total_slots = 0, total_nodes = 0, hist_entries = 0;
     int max_nodes = 0, max_src = 0, max_nkeys = 0;
+    bool all_sheath = true;  // no plates or periodic run: the push without their paths
     Layout L{};
 };
 
@@ -233,6 +234,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         }
         R.inj_ratio = R.w[1] / R.w[0];
         R.geom = plates ? kGeomPlates : periodic ? kGeomPeriodic : kGeomSheath;
+        if (plates || periodic) P.all_sheath = false;
         R.bias = plates ? c.bias : 0.0;
         if (c.steady_window < 0 || !(c.steady_tol >= 0.0)) return SLPIC_EINVAL;
         R.steady_window = c.steady_window > 0 ? c.steady_window : std::max(1, c.nx / 4);
@@ -368,9 +370,9 @@ void l_push(Context* c, bool push, hipStream_t s) {
     const Chunk* ch = push ? c->active : c->a.chunks;
     const int n = push ? c->n_active : (int)c->P.chunks.size();
     if (prec(c) == SLPIC_F32)
-        launch_push_f32(push, per, c->a, ch, n, c->P.tun.block, s);
+        launch_push_f32(push, c->P.all_sheath, per, c->a, ch, n, c->P.tun.block, s);
     else
-        launch_push_f64(push, per, c->a, ch, n, c->P.tun.block, s);
+        launch_push_f64(push, c->P.all_sheath, per, c->a, ch, n, c->P.tun.block, s);
 }
 void l_wall_inject(Context* c, hipStream_t s) {
     if (prec(c) == SLPIC_F32) launch_wall_inject_f32(c->a, s);
