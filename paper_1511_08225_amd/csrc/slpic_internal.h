@@ -21,8 +21,10 @@ constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
 // cells of a 1D run: a moments workgroup keeps 3 FP64 rows of nodes in its
 // 64 KiB of LDS (3 * 8 * 2730 bytes)
 constexpr int kMaxCells = 2729;
-constexpr int kFieldPer = 16;         // field solve: nodes per thread kept in registers
-constexpr int kFieldThreads = 1024;   // field solve: threads of the per-run workgroup, at most
+constexpr int kFieldThreads = 1024;   // field solve: threads of the per-run workgroup
+// field solve: nodes per thread kept in registers (every run's cells fit the
+// 1024-thread workgroup; a longer unrolled row would only cost registers)
+constexpr int kFieldPer = (kMaxCells + kFieldThreads - 1) / kFieldThreads;
 constexpr int kPlatesMaxSource = 511;   // plates: source_cells + 1 nodes fit the injection LDS window
 constexpr int kInjectThreads = 128;     // plates: particles per wall-injection workgroup
 constexpr int kHistoryLen = 4096;  // wall-potential ring per run
