@@ -77,7 +77,8 @@ def traffic_probe(args) -> int:
     cfg = workloads.production_sheath(u_over_vti=args.u, ppc=args.ppc)
     params = launch_params(cfg, args)
     sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
-                    chunk=params["chunk"], block=params["block"], graph_steps=0)
+                    chunk=params["chunk"], block=params["block"], graph_steps=0,
+                    push_order=params.get("push_order", 0))
     sim.step(args.steps)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "traffic", "steps": args.steps, "pushed": sim.pushed_total(), "launch": params}),
@@ -154,7 +155,8 @@ def sweep_bench(args) -> int:
     tune_s = time.perf_counter() - t0
     g = max(16, params["sort_every"])
     sim = slpic.Sim(cfgs, precision=args.precision, sort_every=params["sort_every"],
-                    sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"], graph_steps=g)
+                    sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"], graph_steps=g,
+              push_order=params.get("push_order", 0))
     steps = max(g, (args.steps // g) * g)
     sim.step(g * max(1, args.warmup // g))
     torch.cuda.synchronize()
@@ -224,7 +226,8 @@ def steady_bench(args) -> int:
     g = max(16, params["sort_every"])
     block = g * max(1, 256 // g)
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
-              chunk=params["chunk"], block=params["block"], graph_steps=g)
+              chunk=params["chunk"], block=params["block"], graph_steps=g,
+              push_order=params.get("push_order", 0))
     import torch
     plain = []
     # both sides on a side stream, where blocks of g steps replay as HIP graphs
@@ -303,7 +306,8 @@ def warm_bench(args) -> int:
     eval_cfgs = workloads.batched_sweep(nruns=args.eval_runs, seed=3)
     pred = warmstart.predict(net, std, eval_cfgs)
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
-              chunk=params["chunk"], block=params["block"], graph_steps=g)
+              chunk=params["chunk"], block=params["block"], graph_steps=g,
+              push_order=params.get("push_order", 0))
     cold = slpic.Sim(eval_cfgs, **kw)
     hc, el_c = _histories(cold, len(eval_cfgs), H)
     cold.close()
@@ -642,7 +646,7 @@ def launch_params(cfg, args) -> dict:
     (cached per workload signature) unless given on the command line."""
     from paper_1511_08225_amd import autotune
     if args.no_tune:
-        return {"chunk": args.chunk, "block": 128, "sort_every": args.sort_every, "sort_bucket": 1}
+        return {"chunk": args.chunk, "block": 128, "sort_every": args.sort_every, "sort_bucket": 1, "push_order": 0}
     return autotune.tune([cfg], args.precision, log=lambda m: print(m, file=sys.stderr, flush=True))
 
 
@@ -660,7 +664,7 @@ def run_timed(cfg, args, steps, warmup, params):
     def make():
         return slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"],
                          sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"],
-                         graph_steps=g)
+                         graph_steps=g, push_order=params.get("push_order", 0))
     with torch.cuda.stream(torch.cuda.Stream()):
         sim = make()
         sim.step(warmup)

@@ -139,6 +139,12 @@ typedef struct {
     int32_t retire_steady;/* 1: a run stops advancing (push, source, field solve and */
                           /* step count frozen) from the step after its steady      */
                           /* detector flags it; 0 = every run always advances       */
+    int32_t push_order;   /* order of the push launch's wavefronts: 0 = run by run,  */
+                          /* each species' chunks in slot order; 1 = run by run,    */
+                          /* the two species' chunks interleaved (by first slot).   */
+                          /* Results do not depend on it (but for the order of the  */
+                          /* charge atomics); the faster one depends on the size.   */
+    int32_t reserved;     /* 0                                                      */
 } slpic_tuning;
 
 typedef struct {

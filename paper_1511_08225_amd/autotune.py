@@ -24,8 +24,11 @@ CANDIDATES = {
     "block": (64, 128, 256),
     "sort_every": (8, 16, 32, 64),
     "sort_bucket": (1, 2, 4),
+    "push_order": (0, 1),
 }
-DEFAULT = {"chunk": 512, "block": 128, "sort_every": 16, "sort_bucket": 1}
+DEFAULT = {"chunk": 512, "block": 128, "sort_every": 16, "sort_bucket": 1, "push_order": 0}
+GROUPS = (("chunk", "block"), ("sort_every",), ("sort_bucket",), ("push_order",))
+SWITCH_MARGIN = 0.01  # relative gain a trial needs to replace the incumbent
 CACHE_PATH = os.environ.get("SLPIC_TUNING_CACHE",
                             os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json"))
 
@@ -60,7 +63,8 @@ def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, 
     steps = max(g, (steps // g) * g)
     warmup = max(g, (warmup // g) * g)
     sim = slpic.Sim(configs, precision=precision, sort_every=se, sort_bucket=params["sort_bucket"],
-                    chunk=params["chunk"], block=params["block"], graph_steps=g)
+                    chunk=params["chunk"], block=params["block"], graph_steps=g,
+                    push_order=params.get("push_order", 0))
     try:
         sim.step(warmup)
         torch.cuda.synchronize()
@@ -84,12 +88,20 @@ def tune(configs: list[dict], precision: str = "f32", cache_path: str = CACHE_PA
     measure_fn = measure_fn or measure
     key = signature(configs, precision)
     cache = _load_cache(cache_path)
+    groups, best, earlier = GROUPS, dict(DEFAULT), []
     if not force and key in cache:
-        return dict(cache[key]["params"])
-    best = dict(DEFAULT)
+        cached = cache[key]["params"]
+        if all(k in cached for k in DEFAULT):
+            return dict(cached)
+        # an entry from before a parameter existed: continue from its best
+        # over the groups it lacks (its own trials are kept apart: they were
+        # timed in another session)
+        best = dict(DEFAULT, **cached)
+        groups = tuple(g for g in GROUPS if any(n not in cached for n in g))
+        earlier = cache[key].get("earlier_trials", []) + cache[key].get("trials", [])
     best_t = measure_fn(configs, precision, best, steps, warmup)
     trials = [(dict(best), best_t)]
-    for group in (("chunk", "block"), ("sort_every",), ("sort_bucket",)):
+    for group in groups:
         options = [{}]
         for name in group:
             options = [dict(o, **{name: v}) for o in options for v in CANDIDATES[name]]
@@ -101,10 +113,12 @@ def tune(configs: list[dict], precision: str = "f32", cache_path: str = CACHE_PA
             trials.append((dict(p), t))
             if log:
                 log(f"trial {p}: {t * 1e12:.2f} ps/push")
-            if t < best_t:
+            if t < best_t * (1.0 - SWITCH_MARGIN):  # a change must beat the incumbent beyond noise
                 best, best_t = p, t
     cache[key] = {"params": best, "ps_per_push": best_t * 1e12,
                   "trials": [{"params": p, "ps_per_push": t * 1e12} for p, t in trials]}
+    if earlier:
+        cache[key]["earlier_trials"] = earlier
     os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
     with open(cache_path, "w") as f:
         json.dump(cache, f, indent=1)

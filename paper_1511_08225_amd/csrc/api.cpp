@@ -148,7 +148,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (tin) t = *tin;
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
     if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
-        t.sort_tile < 0 || (t.retire_steady != 0 && t.retire_steady != 1))
+        t.sort_tile < 0 || (t.retire_steady != 0 && t.retire_steady != 1) ||
+        (t.push_order != 0 && t.push_order != 1))
         return SLPIC_EINVAL;
     if (t.block == 0) t.block = 128;
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
@@ -342,6 +343,7 @@ struct Context {
     int sample_every = 0;  // in-step moment sampling period (0: off)
     Chunk* active = nullptr;  // device: the chunks of runs not pruned (the push's work)
     int n_active = 0;
+    std::vector<Chunk> active_host;  // its host copy (the source of the asynchronous upload)
     ~Context() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         for (auto& v : ev)
@@ -464,11 +466,30 @@ int build_graph(Context* c, hipStream_t s) {
     return rc;
 }
 
-// The next unused profiling graph (captured on first use).  Returns nullptr
-// if event records cannot be captured; the caller then launches directly.
 Context* ctx_of(void* p) { return static_cast<Context*>(p); }
 
 // Both particle buffers of (run) hold the current one's slots.
+// The push launch's chunk table: the chunks of the runs not pruned, run by
+// run.  push_order 0 keeps the plan's order (each species' chunks in slot
+// order); 1 interleaves a run's two species by first slot (a stable sort on
+// (run, first slot)): electron and ion chunks cost different arithmetic, and
+// alternating them spreads each kind over the launch, which pays when the
+// whole launch is about one round of resident wavefronts; with many rounds
+// the plan's order, whose neighbouring wavefronts share memory regions, is
+// faster.  Either way a run's chunks past the occupied slots, which return
+// at once, come after its live ones.
+std::vector<Chunk> push_order(const Plan& P) {
+    std::vector<Chunk> act;
+    act.reserve(P.chunks.size());
+    for (const Chunk& ch : P.chunks)
+        if (!P.runs[ch.run].pruned) act.push_back(ch);
+    if (P.tun.push_order == 1)
+        std::stable_sort(act.begin(), act.end(), [](const Chunk& x, const Chunk& y) {
+            return x.run != y.run ? x.run < y.run : x.begin < y.begin;
+        });
+    return act;
+}
+
 int mirror_run(Context* c, int run, hipStream_t s) {
     const RunInfo& R = c->P.runs[run];
     int b = 0;
@@ -586,7 +607,8 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     INIT_TRY(hipMemcpyAsync((void*)a.tiles, c->P.tiles.data(), sizeof(Tile) * c->P.tiles.size(),
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
-    INIT_TRY(hipMemcpyAsync((void*)c->active, c->P.chunks.data(), sizeof(Chunk) * c->P.chunks.size(),
+    c->active_host = push_order(c->P);
+    INIT_TRY(hipMemcpyAsync((void*)c->active, c->active_host.data(), sizeof(Chunk) * c->active_host.size(),
                             hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
     if (!c->P.injb.empty())
         INIT_TRY(hipMemcpyAsync((void*)a.injb, c->P.injb.data(), sizeof(int4) * c->P.injb.size(),
@@ -909,10 +931,8 @@ int slpic_prune_retired(void* ctx, int32_t* h_pruned, void* stream) {
         total += R.pruned;
     }
     if (newly) {
-        std::vector<Chunk> act;
-        act.reserve(c->P.chunks.size());
-        for (const Chunk& ch : c->P.chunks)
-            if (!c->P.runs[ch.run].pruned) act.push_back(ch);
+        c->active_host = push_order(c->P);
+        const std::vector<Chunk>& act = c->active_host;
         if (!act.empty())
             HIP_TRY(hipMemcpyAsync(c->active, act.data(), sizeof(Chunk) * act.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));

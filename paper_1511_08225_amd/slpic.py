@@ -48,7 +48,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32),
                 ("sort_bucket", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("sort_tile", ctypes.c_int32), ("retire_steady", ctypes.c_int32)]
+                ("sort_tile", ctypes.c_int32), ("retire_steady", ctypes.c_int32),
+                ("push_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RunStatus(ctypes.Structure):
@@ -215,12 +216,13 @@ def run_config(cfg: dict) -> RunConfig:
 
 
 def tuning(precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0, graph_steps=0,
-           sort_tile=0, retire_steady=False) -> Tuning:
+           sort_tile=0, retire_steady=False, push_order=0) -> Tuning:
     t = Tuning()
     t.precision = {"f32": SLPIC_F32, "f64": SLPIC_F64}[precision] if isinstance(precision, str) else int(precision)
     t.sort_every, t.sort_bucket, t.chunk, t.block = int(sort_every), int(sort_bucket), int(chunk), int(block)
     t.graph_steps, t.sort_tile = int(graph_steps), int(sort_tile)
     t.retire_steady = int(bool(retire_steady))
+    t.push_order = int(push_order)
     return t
 
 
@@ -250,7 +252,7 @@ class Sim:
     """One or more independent 1D3V sheaths advanced together on one GPU."""
 
     def __init__(self, configs, precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0,
-                 graph_steps=0, sort_tile=0, device="cuda", warm=None, retire_steady=False):
+                 graph_steps=0, sort_tile=0, device="cuda", warm=None, retire_steady=False, push_order=0):
         """warm: optional list (one entry per run) of None or a (5, 256)
         array of predicted profiles (phi, n_e, n_i, Gamma_e, Gamma_i on
         x/L = k/255) for a warm load instead of the cold one."""
@@ -270,7 +272,8 @@ class Sim:
                 a = np.ascontiguousarray(np.asarray(prof, dtype=np.float64).reshape(5, 256))
                 self._warm.append(a)
                 self._cfg[r].warm_profile = a.ctypes.data
-        self._tun = tuning(precision, sort_every, sort_bucket, chunk, block, graph_steps, sort_tile, retire_steady)
+        self._tun = tuning(precision, sort_every, sort_bucket, chunk, block, graph_steps, sort_tile, retire_steady,
+                           push_order)
         L = lib()
         nbytes = L.slpic_workspace_bytes(self._cfg, self.nruns, ctypes.byref(self._tun))
         if nbytes == 0:

@@ -221,13 +221,14 @@ def test_one_step_f32_developed_sheath(gpu_lib, u_over_vti):
         assert fb >= 19
 
 
-def test_one_step_f32_production_size(gpu_lib):
+@pytest.mark.parametrize("push_order", [0, 1])
+def test_one_step_f32_production_size(gpu_lib, push_order):
     """2048 cells, 1000 per cell per species (4,096,000 particles), u = 2 v_ti,
-    in the benchmark's launch configuration."""
+    in the benchmark's launch configuration (either push order)."""
     cfg = workloads.production_sheath(u_over_vti=2.0, sort_every=16)
-    print_case("f32 production size: oracle load")
+    print_case(f"f32 production size, push order {push_order}: oracle load")
     run = oracle.Run(dict(cfg, sort_every=1))
-    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16)
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16, chunk=512, block=64, push_order=push_order)
     push_oracle_to_gpu(sim, 0, run, quantize=True)
     for k in range(2):
         print_case(f"f32 production size step {k}")
@@ -296,9 +297,10 @@ def test_moment_window_matches_oracle_mean_f64(gpu_lib):
     assert not sim.moments_window(0).abs().max().item()
 
 
-def test_batched_runs_match_their_oracles(gpu_lib):
+@pytest.mark.parametrize("push_order", [0, 1])
+def test_batched_runs_match_their_oracles(gpu_lib, push_order):
     """Ragged runs in one context (different cells, ppc, ion mass, speed
-    limit) each match their own oracle after one step."""
+    limit) each match their own oracle after one step (either push order)."""
     cfgs = workloads.batched_sweep(nruns=3, seed=9, cells_range=(64, 200), ppc_range=(20, 60),
                                    sort_every=1)
     runs = []
@@ -306,7 +308,7 @@ def test_batched_runs_match_their_oracles(gpu_lib):
         r = oracle.Run(c)
         r.step(10)
         runs.append(r)
-    sim = gpu_lib.Sim(cfgs, precision="f64", sort_every=1)
+    sim = gpu_lib.Sim(cfgs, precision="f64", sort_every=1, chunk=64, push_order=push_order)
     for r, run in enumerate(runs):
         push_oracle_to_gpu(sim, r, run, quantize=False)
     sim.step(1)
