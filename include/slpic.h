@@ -144,7 +144,7 @@ typedef struct {
                           /* the two species' chunks interleaved (by first slot).   */
                           /* Results do not depend on it (but for the order of the  */
                           /* charge atomics); the faster one depends on the size.   */
-    int32_t reserved;     /* 0                                                      */
+    int32_t reserved;     /* must be 0 (SLPIC_EINVAL otherwise)                     */
 } slpic_tuning;
 
 typedef struct {

@@ -149,7 +149,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
     if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
         t.sort_tile < 0 || (t.retire_steady != 0 && t.retire_steady != 1) ||
-        (t.push_order != 0 && t.push_order != 1))
+        (t.push_order != 0 && t.push_order != 1) || t.reserved != 0)
         return SLPIC_EINVAL;
     if (t.block == 0) t.block = 128;
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);

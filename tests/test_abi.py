@@ -57,6 +57,9 @@ def test_workspace_planning_validates_configs():
     for order, ok in ((0, True), (1, True), (2, False), (-1, False)):
         to = slpic.tuning("f32", push_order=order)
         assert (L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(to)) > 0) == ok, order
+    tr = slpic.tuning("f32")
+    tr.reserved = 1
+    assert L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(tr)) == 0
     inf = slpic.run_config(workloads.sheath(nx=64, ppc=10, u_over_vti=math.inf))
     assert L.slpic_workspace_bytes(ctypes.byref(inf), 1, ctypes.byref(t)) > 0
 
