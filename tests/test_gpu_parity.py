@@ -221,12 +221,14 @@ def test_one_step_f32_developed_sheath(gpu_lib, u_over_vti):
         assert fb >= 19
 
 
-@pytest.mark.parametrize("push_order", [0, 1])
-def test_one_step_f32_production_size(gpu_lib, push_order):
-    """2048 cells, 1000 per cell per species (4,096,000 particles), u = 2 v_ti,
-    in the benchmark's launch configuration (either push order)."""
-    cfg = workloads.production_sheath(u_over_vti=2.0, sort_every=16)
-    print_case(f"f32 production size, push order {push_order}: oracle load")
+@pytest.mark.parametrize("u_over_vti,push_order", [(2.0, 0), (2.0, 1), (5.0, 1), (10.0, 1), (math.inf, 1)])
+def test_one_step_f32_production_size(gpu_lib, u_over_vti, push_order):
+    """2048 cells, 1000 per cell per species (4,096,000 particles), every
+    speed limit of the production sweep u in {2, 5, 10, inf} v_ti (inf: the
+    PIC step dx/(5 v_te)), in the benchmark's launch configuration (either
+    push order at u = 2 v_ti)."""
+    cfg = workloads.production_sheath(u_over_vti=u_over_vti, sort_every=16)
+    print_case(f"f32 production size, u/vti={u_over_vti}, push order {push_order}: oracle load")
     run = oracle.Run(dict(cfg, sort_every=1))
     sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16, chunk=512, block=64, push_order=push_order)
     push_oracle_to_gpu(sim, 0, run, quantize=True)
@@ -244,11 +246,17 @@ def test_one_step_f32_production_size(gpu_lib, push_order):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("bucket", [1, 4, 0])
-def test_sort_permutation_bit_exact(gpu_lib, prec, bucket):
+@pytest.mark.parametrize("sort_tile", [0, 512, 2048])
+def test_sort_permutation_bit_exact(gpu_lib, prec, bucket, sort_tile):
+    """Stable cell sort with compaction, bit-exact against the oracle's.  The
+    9600 slots per species are one sort tile by default (16384 slots) and 19
+    or 5 tiles at 512 or 2048 slots, so the scan of per-tile key counts across
+    tiles is exercised."""
     cfg = workloads.small_sheath(sort_every=0, sort_bucket=bucket if bucket else 0, seed=6)
     run = oracle.Run(cfg)
     run.step(40)  # dead slots and appended injections in place
-    sim = gpu_lib.Sim(cfg, precision=prec, sort_every=0, sort_bucket=bucket)
+    print_case(f"sort {prec} bucket={bucket} sort_tile={sort_tile}")
+    sim = gpu_lib.Sim(cfg, precision=prec, sort_every=0, sort_bucket=bucket, sort_tile=sort_tile)
     push_oracle_to_gpu(sim, 0, run, quantize=(prec == "f32"))
     before = [oracle_state(run, s) for s in range(2)]
     assert any((b[0] < 0).any() for b in before)
@@ -261,6 +269,38 @@ def test_sort_permutation_bit_exact(gpu_lib, prec, bucket):
         xo, vxo, vpo = oracle_state(run, s)
         assert np.array_equal(xg, xo)
         assert np.array_equal(vxg, vxo)
+
+
+@pytest.mark.parametrize("bucket", [1, 4])
+def test_sort_permutation_production_size(gpu_lib, bucket):
+    """The production sheath (4,096,000 particles, 3,072,000 slots per species:
+    188 sort tiles of 16384 slots each) sorted after 24 unsorted steps, in the
+    benchmark's launch configuration: permutation and sorted particles
+    bit-exact against the oracle's stable sort of the GPU's own positions."""
+    cfg = workloads.production_sheath(u_over_vti=2.0, sort_every=0, sort_bucket=bucket)
+    print_case(f"production-size sort, bucket {bucket}: 24 steps")
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=0, sort_bucket=bucket, chunk=512, block=64, push_order=1)
+    sim.step(24)
+    run = oracle.Run(cfg, load=False)
+    before = []
+    for s in range(2):
+        x, vx, vp2 = sim.export_particles(0, s)
+        assert (x < 0).any()  # absorbed slots to drop
+        set_oracle_particles(run, s, x, vx, vp2)
+        before.append((x, vx, vp2))
+    print_case(f"production-size sort, bucket {bucket}: sort")
+    sim.sort_now()
+    perms = run.sort()
+    for s in range(2):
+        pg = sim.perm(0, s)
+        assert len(pg) > 2 * 16384
+        assert np.array_equal(pg, perms[s]), s
+        xg, vxg, vpg = sim.export_particles(0, s)
+        x, vx, vp2 = before[s]
+        assert np.array_equal(xg, x[perms[s]])
+        assert np.array_equal(vxg, vx[perms[s]])
+        assert np.array_equal(vpg, vp2[perms[s]])
+    sim.close()
 
 
 def test_moments_match_oracle_f64(gpu_lib):

@@ -167,6 +167,44 @@ def test_deposit2d_matches_oracle(gpu_lib, prec, sorted_):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_deposit_and_step2d_at_full_tile_occupancy(gpu_lib, prec):
+    """The 2D sheath's occupancy (64 per cell per species, 8 x 8-cell tiles:
+    4096 particles per tile and species, 16 passes of the 256-thread tile
+    loop) on a 64 x 64-cell grid: grid charge element by element after the
+    sort (tile windows) and after one step, against the oracle."""
+    cfg = workloads.sheath2d(nx=64, ny=64, ppc=64, tile=8, sort_every=8, seed=41)
+    ny = cfg["ny"]
+    print_case(f"2d full tile occupancy {prec}: oracle load + 3 steps")
+    run = oracle.Run2D(cfg, ny, tile=8)
+    run.step(3)
+    run = _with_sort_every(run, cfg, ny, 1)
+    sim = gpu_lib.Sim2D(cfg, ny, precision=prec, sort_every=1, tile=8)
+    _push_to_gpu(sim, run, quantize=(prec == "f32"))
+    sim.sort_now()
+    run.sort()
+    run.refresh_fields()
+    sim.refresh_fields()
+    x0 = run.particles(0)[0]
+    per_col = np.bincount(x0[x0 >= 0].astype(np.int64) // 8, minlength=8)
+    assert per_col.max() >= 4096 * 8 * 0.9  # a column of 8 tiles holds ~8 x 4096
+    tol = 1e-12 if prec == "f64" else 1e-5
+    g, o = sim.grid(), run.grid()
+    for s in range(2):
+        assert rel_inf(g["Q"][s], o["Q"][s]) <= tol, ("sorted deposit", s)
+    print_case(f"2d full tile occupancy {prec}: one step")
+    sim.step(1)
+    run.step(1)
+    g, o = sim.grid(), run.grid()
+    for s in range(2):
+        assert rel_inf(g["Q"][s], o["Q"][s]) <= tol, ("step", s, rel_inf(g["Q"][s], o["Q"][s]))
+    if prec == "f64":
+        st = sim.status()
+        assert st["nslots"] == [run.nslots(0), run.nslots(1)]
+        _compare(sim, run, tol_q=1e-12, tol_x=1e-11, tol_v=1e-11)
+    sim.close()
+
+
 def _with_sort_every(run, cfg, ny, sort_every):
     """A copy of an oracle run whose periodic sort runs every sort_every steps."""
     r2 = oracle.Run2D(dict(cfg, sort_every=sort_every), ny, tile=run.tile, load=False)
@@ -317,6 +355,18 @@ def test_full_size_2d_f32_sampled_and_properties(gpu_lib):
         beta = np.where(s2 <= u * u, 1.0, u / np.sqrt(np.maximum(s2, 1e-300)))
         want = cfg["species"][s]["charge"] * sim.status()["weight"][s] * beta.sum()
         assert g1["Q"][s].sum() == pytest.approx(want, rel=1e-9)
+    # the step's charge element by element: the oracle's deposit of the GPU's own particles
+    print_case("2d full size: oracle deposit of the GPU's particles")
+    ref = oracle.Run2D(cfg, ny, tile=cfg["tile"], load=False)
+    for s in range(2):
+        X, Y, VX, VY, VZ2 = sim.export_particles(s)
+        ref.set_particles(s, X, Y, VX, VY, np.sqrt(VZ2))
+        del X, Y, VX, VY, VZ2
+    ref.refresh_fields()
+    o1 = ref.grid()
+    for s in range(2):
+        assert rel_inf(g1["Q"][s], o1["Q"][s]) <= 1e-5, ("full-size charge", s, rel_inf(g1["Q"][s], o1["Q"][s]))
+    del ref
     # Poisson and E at full size
     res, rho = _five_point_residual(g1["phi"], g1["Q"][0] + g1["Q"][1], cfg["dx"])
     assert np.abs(res).max() <= 1e-9 * np.abs(rho).max()
