@@ -72,7 +72,9 @@ enum {
     SLPIC_ECAPACITY = -3,  /* particle buffer full (sticky device flag)   */
     SLPIC_ENUMERIC = -4,   /* non-finite particle state (sticky flag)      */
     SLPIC_EHIP = -5,       /* a HIP runtime call failed                    */
-    SLPIC_ESTATE = -6      /* call not valid in the context's state        */
+    SLPIC_ESTATE = -6,     /* call not valid in the context's state        */
+    SLPIC_ELIMIT = -7      /* input larger than an allocation-free call's  */
+                           /* fixed scratch                                */
 };
 
 /* Speed-limiting function: Eq. (11b) (default) or Eq. (11a). */
@@ -378,6 +380,21 @@ int slpic_mlp_to_bf16(const float* d_params_fp32, void* d_params_bf16, void* str
  * activations backward needs. */
 int slpic_mlp_forward(const void* d_params_bf16, const float* d_x, float* d_y, int32_t batch, void* d_act,
                       void* stream);
+
+/* Allocation-free variant of slpic_mlp_forward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same d_y, with
+ * the activations in a fixed array of the library's code object instead of
+ * a caller buffer (SLPIC_MLP_NOALLOC_MAX_BATCH x 772 BF16 = 1.5 MiB, held on
+ * every GPU the library runs on until the process ends).  It calls no
+ * allocator.  The first call on a device (that device current) looks up the
+ * array's address there.  batch beyond SLPIC_MLP_NOALLOC_MAX_BATCH returns
+ * SLPIC_ELIMIT; nothing else is retained between calls (every call rewrites
+ * the activations it reads).  Calls that overlap on one GPU (other streams,
+ * other threads) share the array and race: serialise them. */
+#define SLPIC_MLP_NOALLOC_MAX_BATCH 1024
+int slpic_mlp_forward_noalloc(const void* d_params_bf16, const float* d_x, float* d_y, int32_t batch,
+                              void* stream);
 
 /* d_grads [SLPIC_MLP_PARAMS] (FP32, overwritten) = gradient of
  * sum(d_dy * y) for the batch whose activations forward left in d_act. */

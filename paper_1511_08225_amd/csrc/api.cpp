@@ -1084,6 +1084,7 @@ const char* slpic_strerror(int code) {
         case SLPIC_ENUMERIC: return "non-finite particle state";
         case SLPIC_EHIP: return "HIP runtime error";
         case SLPIC_ESTATE: return "call not valid in this state";
+        case SLPIC_ELIMIT: return "input larger than the allocation-free call's fixed scratch";
         default: return "unknown error";
     }
 }

@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "slpic.h"
 
@@ -178,6 +179,50 @@ using namespace slpic_mlp;
 
 static int last_error() { return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP; }
 
+// The forward pass on caller buffers: BF16 inputs and the three hidden
+// activations go to act ([batch][4 + 3 * 256] BF16), the output to y.
+static int forward_impl(const bf16* P, const float* x, float* y, int32_t batch, bf16* act, hipStream_t s) {
+    bf16* xr = act;
+    bf16* h1 = xr + (int64_t)batch * kIn;
+    bf16* h2 = h1 + (int64_t)batch * kHid;
+    bf16* h3 = h2 + (int64_t)batch * kHid;
+    const int64_t n1 = (int64_t)batch * kHid;
+    hipLaunchKernelGGL(k_layer1, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, P, x, batch, xr, h1);
+    // h_{l+1}[b][n] = relu(sum_k h_l[b][k] W[n][k] + b[n])
+    gemm<kHidden>(h1, kHid, 1, P + oW2, 1, kHid, batch, kHid, kHid, P + ob2, nullptr, h2, kHid, s);
+    gemm<kHidden>(h2, kHid, 1, P + oW3, 1, kHid, batch, kHid, kHid, P + ob3, nullptr, h3, kHid, s);
+    gemm<kOutput>(h3, kHid, 1, P + oW4, 1, kHid, batch, kOut, kHid, P + ob4, nullptr, y, kOut, s);
+    return last_error();
+}
+
+// Activation scratch of the allocation-free forward pass: a fixed array in
+// device memory, one copy per GPU (loaded with the code object), never
+// allocated at run time.  Host code only ever uses the address
+// hipGetSymbolAddress returns for the current device: the array's name is a
+// host-side stand-in.  Calls that overlap on one GPU share it and race.
+constexpr int kNoAllocMaxBatch = SLPIC_MLP_NOALLOC_MAX_BATCH;
+constexpr int64_t kNoAllocScratch = (int64_t)kNoAllocMaxBatch * (kIn + 3 * kHid);
+static __device__ __align__(256) bf16 scratch[kNoAllocScratch];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];  // device address of scratch, per device ordinal
+
+// The current device's scratch address, looked up on the first call on that
+// device (with it current) and kept.
+static int noalloc_scratch(bf16** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SLPIC_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SLPIC_EHIP;
+        g_scratch_dev[dev] = p;
+    }
+    *out = (bf16*)g_scratch_dev[dev];
+    return SLPIC_OK;
+}
+
 extern "C" {
 
 size_t slpic_mlp_act_bytes(int32_t batch) {
@@ -198,19 +243,17 @@ int slpic_mlp_to_bf16(const float* d_params_fp32, void* d_params_bf16, void* str
 int slpic_mlp_forward(const void* d_params_bf16, const float* d_x, float* d_y, int32_t batch, void* d_act,
                       void* stream) {
     if (!d_params_bf16 || !d_x || !d_y || !d_act || batch <= 0 || batch % 16) return SLPIC_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    const bf16* P = (const bf16*)d_params_bf16;
-    bf16* xr = (bf16*)d_act;
-    bf16* h1 = xr + (int64_t)batch * kIn;
-    bf16* h2 = h1 + (int64_t)batch * kHid;
-    bf16* h3 = h2 + (int64_t)batch * kHid;
-    const int64_t n1 = (int64_t)batch * kHid;
-    hipLaunchKernelGGL(k_layer1, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, P, d_x, batch, xr, h1);
-    // h_{l+1}[b][n] = relu(sum_k h_l[b][k] W[n][k] + b[n])
-    gemm<kHidden>(h1, kHid, 1, P + oW2, 1, kHid, batch, kHid, kHid, P + ob2, nullptr, h2, kHid, s);
-    gemm<kHidden>(h2, kHid, 1, P + oW3, 1, kHid, batch, kHid, kHid, P + ob3, nullptr, h3, kHid, s);
-    gemm<kOutput>(h3, kHid, 1, P + oW4, 1, kHid, batch, kOut, kHid, P + ob4, nullptr, d_y, kOut, s);
-    return last_error();
+    return forward_impl((const bf16*)d_params_bf16, d_x, d_y, batch, (bf16*)d_act, (hipStream_t)stream);
+}
+
+int slpic_mlp_forward_noalloc(const void* d_params_bf16, const float* d_x, float* d_y, int32_t batch,
+                              void* stream) {
+    if (!d_params_bf16 || !d_x || !d_y || batch <= 0 || batch % 16) return SLPIC_EINVAL;
+    if (batch > kNoAllocMaxBatch) return SLPIC_ELIMIT;
+    bf16* act = nullptr;
+    const int rc = noalloc_scratch(&act);
+    if (rc != SLPIC_OK) return rc;
+    return forward_impl((const bf16*)d_params_bf16, d_x, d_y, batch, act, (hipStream_t)stream);
 }
 
 int slpic_mlp_backward(const void* d_params_bf16, const void* d_act, const float* d_dy, float* d_grads,

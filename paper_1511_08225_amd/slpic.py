@@ -127,6 +127,7 @@ def lib():
             "slpic_mlp_work_bytes": (ctypes.c_size_t, [i32]),
             "slpic_mlp_to_bf16": (ctypes.c_int, [_P, _P, _P]),
             "slpic_mlp_forward": (ctypes.c_int, [_P, _P, _P, i32, _P, _P]),
+            "slpic_mlp_forward_noalloc": (ctypes.c_int, [_P, _P, _P, i32, _P]),
             "slpic_mlp_backward": (ctypes.c_int, [_P, _P, _P, _P, i32, _P, _P]),
             "slpic_mlp_mse": (ctypes.c_int, [_P, _P, _P, i64, _P, _P]),
             "slpic_mlp_adam": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
@@ -438,6 +439,7 @@ def fixed_point_round(xt: np.ndarray, fixed_bits: int) -> np.ndarray:
 
 # ---------------------------------------------------------------- warm-start network
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 4, 256, 1280, 461824
+MLP_NOALLOC_MAX_BATCH = 1024
 
 
 class Mlp:
@@ -476,6 +478,20 @@ class Mlp:
         _check(lib().slpic_mlp_forward(_P(self.pbf16.data_ptr()), _P(x.data_ptr()), _P(self.y.data_ptr()),
                                        self.batch, _P(self.act.data_ptr()), self._stream()), "slpic_mlp_forward")
         return self.y
+
+    def forward_noalloc(self, x, y=None) -> torch.Tensor:
+        """The same forward pass through slpic_mlp_forward_noalloc: the
+        activations stay in the library's fixed device array (nothing for
+        backward); y [n][1280] is written for x [n][4], n a multiple of 16 up
+        to MLP_NOALLOC_MAX_BATCH."""
+        x = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
+        if x.dim() != 2 or x.shape[1] != MLP_IN:
+            raise SlpicError("x must be [n][4]")
+        if y is None:
+            y = torch.empty((x.shape[0], MLP_OUT), dtype=torch.float32, device=self.device)
+        _check(lib().slpic_mlp_forward_noalloc(_P(self.pbf16.data_ptr()), _P(x.data_ptr()), _P(y.data_ptr()),
+                                               int(x.shape[0]), self._stream()), "slpic_mlp_forward_noalloc")
+        return y
 
     def backward(self, dy) -> torch.Tensor:
         """FP32 gradient of sum(dy * y) for the last forward batch."""
