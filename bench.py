@@ -52,25 +52,36 @@ def cpu_baseline(cfg: dict, budget_s: float = 12.0) -> dict:
                       f"FP64 C oracle, one thread"}
 
 
-def traffic_probe(args) -> int:
-    """The workload for the HBM traffic counters: a 1 GiB device copy (the
-    calibration kernel, 1 GiB read + 1 GiB written), then direct-launch steps
-    of the benchmark workload, so that every push dispatch is counted."""
+def _copy_calibration():
+    """The calibration kernel of the traffic counters: a 1 GiB device copy
+    (1 GiB read + 1 GiB written)."""
     import torch
-    import workloads
-    from paper_1511_08225_amd import slpic
     src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
     torch.cuda.empty_cache()
+
+
+def traffic_probe(args) -> int:
+    """The workload for the counter runs (rocprofv3 --pmc): the benchmark's
+    warm-up steps, then the 1 GiB copy that calibrates the traffic counters,
+    then --steps direct-launch steps, so that the push dispatches after the
+    copy are those of the timed region's particle states (steps after the
+    warm-up), each one counted."""
+    import torch
+    import workloads
+    from paper_1511_08225_amd import slpic
     if args.only_2d:
         cfg = workloads.sheath2d()
         sim = slpic.Sim2D(cfg, cfg["ny"], precision=args.precision, sort_every=cfg["sort_every"], tile=cfg["tile"])
+        sim.step(args.warmup)
+        torch.cuda.synchronize()
+        _copy_calibration()
         sim.step(args.steps)
         torch.cuda.synchronize()
-        print(json.dumps({"probe": "traffic", "workload": "sheath2d", "steps": args.steps,
+        print(json.dumps({"probe": "traffic", "workload": "sheath2d", "warmup": args.warmup, "steps": args.steps,
                           "pushed": sim.status()["pushed_total"]}), flush=True)
         sim.close()
         return 0
@@ -79,12 +90,30 @@ def traffic_probe(args) -> int:
     sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
                     chunk=params["chunk"], block=params["block"], graph_steps=0,
                     push_order=params.get("push_order", 0))
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    _copy_calibration()
     sim.step(args.steps)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "traffic", "steps": args.steps, "pushed": sim.pushed_total(), "launch": params}),
-          flush=True)
+    print(json.dumps({"probe": "traffic", "warmup": args.warmup, "steps": args.steps, "pushed": sim.pushed_total(),
+                      "launch": params}), flush=True)
     sim.close()
     return 0
+
+
+def after_copy(rows):
+    """Counter rows of the dispatches that follow the calibration copy (the
+    probe's steps after its warm-up), in dispatch order."""
+    key = "Dispatch_Id" if rows and "Dispatch_Id" in rows[0] else None
+    if key:
+        rows = sorted(rows, key=lambda r: int(r[key]))
+    grid = "Grid_Size" if rows and "Grid_Size" in rows[0] else "Grid_Size_X"  # counter / kernel-trace files
+    copies = [(int(r[grid]), i) for i, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"]]
+    if not copies:
+        return rows
+    big = max(g for g, _ in copies)  # the calibration copy: the largest grid (other copies move small tables)
+    first = min(i for g, i in copies if g == big)
+    return rows[first:]
 
 
 def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int, two_d: bool = False) -> int:
@@ -95,7 +124,7 @@ def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int, two_d: bo
     kernel = "k_push2d" if two_d else "k_push_deposit"
 
     def per_kernel(path, counter):
-        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows = after_copy([r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter])
         copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         push = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]
                 and ", true," in r["Kernel_Name"]]
