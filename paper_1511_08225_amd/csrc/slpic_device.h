@@ -218,8 +218,9 @@ __device__ __forceinline__ T series_inverse(T al, T kap) {
     return kap * (T(1) + kap * (c2 + kap * (c3 + kap * (c4 + kap * (c5 + kap * (c6 + kap * (c7 + kap * c8)))))));
 }
 
-// The same series through kappa^4: for kappa <= 0.01 the first omitted term
-// c_5 kappa^5 (|c_5| <= 4 for |alpha| <= 1) is below 4e-10 s0.
+// The same series through kappa^4: for kappa <= 0.03 the omitted terms sum
+// to at most 2.2e-8 s0 for every |alpha| <= 1 (the leading one, c_5 kappa^5
+// with |c_5| <= 0.875), under the float rounding of s0.
 template <typename T>
 __device__ __forceinline__ T series_inverse4(T al, T kap) {
     const T a2 = al * al;
@@ -233,7 +234,7 @@ __device__ __forceinline__ T series_inverse4(T al, T kap) {
 //  - c = 0: closed form, p1|p1| = p0|p0| + 2K.
 //  - kappa = K/s0^2 < 1/4: the series inverse, used as is in float when
 //    kappa <= 0.11 (truncation below float rounding; through kappa^4 when
-//    every active lane of the wave has kappa <= 0.01), else refined by
+//    every active lane of the wave has kappa <= 0.03), else refined by
 //    Newton steps on G;
 //  - larger kicks: Newton on G from the upper bound min(c = 0 solution,
 //    p0 + K/c), bracketed by bisection (G is monotone).
@@ -250,7 +251,7 @@ __device__ __forceinline__ T fast_advance(T c2, T p0, T K, int* iters = nullptr)
         const T s0 = Fm<T>::sqrt(p0 * p0 + c2);
         const T inv_s0 = Fm<T>::rcp(s0);
         const T kap = K * inv_s0 * inv_s0;
-        if (f32 && __all(kap <= T(0.01))) {  // the whole wave's kicks are small: four terms
+        if (f32 && __all(kap <= T(0.03))) {  // the whole wave's kicks are small: four terms
             if (iters) *iters += 1;
             return p0 + s0 * series_inverse4(p0 * inv_s0, kap);
         }
