@@ -395,23 +395,31 @@ def _histories(sim, nruns, steps):
 
 
 def warm_bench(args) -> int:
-    """Learned warm start end to end: steady profiles from batched cold runs
-    (training sweep), network training in the library's kernels, then
-    held-out runs loaded cold and warm; time to the steady wall potential
-    (within 2 % of the cold run's late mean for three windows of nx/4 steps)."""
+    """Learned warm start end to end at the C5 scale: steady profiles
+    (phi, n, Gamma, T per species) of --train-runs batched cold runs (seed 2)
+    over --horizon steps, the network trained on them in the library's
+    kernels, then --eval-runs held-out runs (seed 3).  Reports (1) the
+    prediction of the late wall potential against the held-out cold runs
+    (the judge: their mean over the last quarter of the horizon) beside the
+    naive prediction (the training mean) and beside the cold runs' own
+    running estimate, with the cold steps each prediction is worth; (2) the
+    held-out runs loaded warm from the prediction, and from their own late
+    profiles (a perfect prediction), against the cold reference, and the
+    batched warm vs plain cold wall time to the steady criterion."""
     import numpy as np
+    import torch
     import workloads
     from paper_1511_08225_amd import autotune, slpic, warmstart
     H = args.horizon
     g = 64
-    block = max(16, args.steps // 16 * 16)
     t_all = time.perf_counter()
     train_cfgs = workloads.batched_sweep(nruns=args.train_runs, seed=2)
     params = autotune.tune(train_cfgs[:256], args.precision)
     profs, t_col = [], time.perf_counter()
     for k in range(0, len(train_cfgs), 256):
-        p, _ = warmstart.collect_profiles(train_cfgs[k:k + 256], steps=H, tuning=params)
+        p, _ = warmstart.collect_profiles(train_cfgs[k:k + 256], steps=H, sample_last=H // 4, tuning=params)
         profs.append(p)
+        print(f"collected {k + len(p)} / {len(train_cfgs)} training profiles", file=sys.stderr, flush=True)
     Y = np.concatenate(profs)
     X = np.stack([warmstart.features(c) for c in train_cfgs])
     t_col = time.perf_counter() - t_col
@@ -420,74 +428,95 @@ def warm_bench(args) -> int:
                                        log=lambda m: print(m, file=sys.stderr, flush=True))
     t_tr = time.perf_counter() - t_tr
     eval_cfgs = workloads.batched_sweep(nruns=args.eval_runs, seed=3)
+    t_pred = time.perf_counter()
     pred = warmstart.predict(net, std, eval_cfgs)
+    t_pred = time.perf_counter() - t_pred
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
               chunk=params["chunk"], block=params["block"], graph_steps=g,
               push_order=params.get("push_order", 0))
+    n = len(eval_cfgs)
+    W = [max(1, c["nx"] // 4) for c in eval_cfgs]
     cold = slpic.Sim(eval_cfgs, **kw)
-    hc, el_c = _histories(cold, len(eval_cfgs), H)
+    hc, el_c = _histories(cold, n, H)
     cold.close()
-    warm = slpic.Sim(eval_cfgs, warm=list(warmstart.quasi_neutral(pred)), **kw)
-    hw, el_w = _histories(warm, len(eval_cfgs), H)
-    warm.close()
     ref = hc[:, -H // 4:].mean(axis=1)
-    tc = [warmstart.steady_index(hc[r], max(1, c["nx"] // 4), ref[r]) for r, c in enumerate(eval_cfgs)]
-    tw = [warmstart.steady_index(hw[r], max(1, c["nx"] // 4), ref[r]) for r, c in enumerate(eval_cfgs)]
-    # each run against its own late mean (cold against cold, warm against warm)
-    ref_w = hw[:, -H // 4:].mean(axis=1)
-    self_c = [warmstart.steady_index(hc[r], max(1, c["nx"] // 4), ref[r], 0.05) for r, c in enumerate(eval_cfgs)]
-    self_w = [warmstart.steady_index(hw[r], max(1, c["nx"] // 4), ref_w[r], 0.05) for r, c in enumerate(eval_cfgs)]
-    # u above sqrt(3) c_s: the speed-limited electrons respond faster than the ions
-    valid = [c["u_over_vti"] > math.sqrt(3.0 * c["te_over_ti"]) for c in eval_cfgs]
+    # (1) the prediction of the late wall potential
+    pw = pred[:, 0, 0] - pred[:, 0, -1]
+    naive = float((Y[:, 0, 0] - Y[:, 0, -1]).mean())
+    e_net = np.abs(pw - ref) / np.abs(ref)
+    e_naive = np.abs(naive - ref) / np.abs(ref)
+
+    def cold_estimate_err(t):
+        return np.array([abs(hc[r, t - W[r]:t].mean() - ref[r]) / abs(ref[r]) for r in range(n)])
+
+    def steps_worth(r, err):  # cold steps until its window estimate stays (3 windows) within err
+        nw = H // W[r]
+        means = hc[r, :nw * W[r]].reshape(nw, W[r]).mean(axis=1)
+        ok = np.abs(means - ref[r]) <= err * abs(ref[r])
+        for k in range(nw - 2):
+            if ok[k] and ok[k + 1] and ok[k + 2]:
+                return (k + 1) * W[r]
+        return H
+
+    worth_net = [steps_worth(r, e_net[r]) for r in range(n)]
+    worth_naive = [steps_worth(r, e_naive[r]) for r in range(n)]
+    prediction = {
+        "judge": "held-out cold run: mean Phi_w over the last quarter of the horizon",
+        "median_rel_err_network": float(np.median(e_net)), "median_rel_err_naive_mean": float(np.median(e_naive)),
+        "network_better_than_naive": int((e_net < e_naive).sum()),
+        "median_rel_err_cold_estimate": {f"H/{d}": float(np.median(cold_estimate_err(H // d))) for d in (8, 4, 2)},
+        "cold_steps_worth_median": {"network": float(np.median(worth_net)), "naive_mean": float(np.median(worth_naive))},
+        "note": "cold steps worth: the steps a cold run needs until its window estimate of Phi_w stays within "
+                "the prediction's error of the reference (the horizon if never)",
+        "predict_seconds": t_pred,
+    }
+    # (2) warm loads: from the prediction, and from the held-out runs' own late profiles
+    warm = slpic.Sim(eval_cfgs, warm=list(warmstart.quasi_neutral(pred)), **kw)
+    hw, el_w = _histories(warm, n, H)
+    warm.close()
+    own, _ = warmstart.collect_profiles(eval_cfgs, steps=H, sample_last=H // 4, tuning=params)
+    perfect = slpic.Sim(eval_cfgs, warm=list(warmstart.quasi_neutral(own)), **kw)
+    hp, _ = _histories(perfect, n, H)
+    perfect.close()
+    tc = [warmstart.steady_index(hc[r], W[r], ref[r]) for r in range(n)]
+    tw = [warmstart.steady_index(hw[r], W[r], ref[r]) for r in range(n)]
     reach = {}
     for tol in (0.02, 0.05, 0.1):
-        reach[str(tol)] = [sum(warmstart.steady_index(h[r], max(1, c["nx"] // 4), ref[r], tol) >= 0
-                               for r, c in enumerate(eval_cfgs)) for h in (hc, hw)]
+        reach[str(tol)] = {name: int(sum(warmstart.steady_index(h[r], W[r], ref[r], tol) >= 0 for r in range(n)))
+                           for name, h in (("cold", hc), ("warm_predicted", hw), ("warm_own_late_profiles", hp))}
+    late = lambda h: h[:, -H // 4:].mean(axis=1)  # noqa: E731
     # plain: each run alone, step time measured per run
     tau1 = []
-    for c in eval_cfgs:
+    for c in eval_cfgs[:min(64, n)]:
         one = slpic.Sim([dict(c, run=0)], **kw)
         one.step(g)
-        import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         one.step(4 * g)
         torch.cuda.synchronize()
         tau1.append((time.perf_counter() - t0) / (4 * g))
         one.close()
-    tau_b = el_c / H
+    tau1 = float(np.mean(tau1))
     steps_c = [t if t >= 0 else H for t in tc]
     steps_w = [t if t >= 0 else H for t in tw]
-    plain_s = float(sum(s * t for s, t in zip(steps_c, tau1)))
-    batched_cold_s = max(steps_c) * tau_b
+    plain_s = float(sum(steps_c)) * tau1
     batched_warm_s = max(steps_w) * el_w / H
     censored_c, censored_w = any(t < 0 for t in tc), any(t < 0 for t in tw)
-    pred_phi = pred[:, 0, 0] - pred[:, 0, -1]
     print(json.dumps({
-        "metric": "time-to-steady-sheath, batched+warm-start vs plain", "unit": "s",
-        "horizon_steps": H, "train_runs": len(train_cfgs), "eval_runs": len(eval_cfgs), "tuned": params,
+        "metric": "learned warm start: prediction of the late sheath, and time to the steady sheath, "
+                  "batched+warm-start vs plain", "unit": "s",
+        "horizon_steps": H, "train_runs": len(train_cfgs), "eval_runs": n, "tuned": params,
+        "prediction": prediction,
         "criterion": "window mean of Phi_w (nx/4 steps) within 2% of the cold run's mean over its last 25%, "
                      "for three windows",
-        "censored_note": "runs not steady within the horizon count as the horizon: with censoring the "
-                         "times are bounds and their ratio is not a measured speedup",
-        "plain_seconds": plain_s, "plain_censored": censored_c,
-        "batched_cold_seconds": batched_cold_s, "batched_warm_seconds": batched_warm_s,
-        "batched_warm_censored": censored_w,
+        "reached_by_tol": reach,
+        "late_phi_w_ratio_median": {"warm_predicted": float(np.median(late(hw) / ref)),
+                                    "warm_own_late_profiles": float(np.median(late(hp) / ref))},
+        "plain_seconds_estimate": plain_s, "plain_censored": censored_c,
+        "batched_warm_seconds": batched_warm_s, "batched_warm_censored": censored_w,
         "speedup_batched_warm_vs_plain": (plain_s / batched_warm_s
                                           if batched_warm_s > 0 and not (censored_c or censored_w) else None),
-        "batched_step_ms": tau_b * 1e3, "plain_step_ms_mean": float(np.mean(tau1)) * 1e3,
-        "reached_cold": int(sum(t >= 0 for t in tc)), "reached_warm": int(sum(t >= 0 for t in tw)),
-        "reached_cold_warm_by_tol": reach,
-        "self_referenced_5pct": {
-            "note": "each run against the mean of its own last 25 % (warm runs settle in another state)",
-            "reached_cold": int(sum(t >= 0 for t in self_c)), "reached_warm": int(sum(t >= 0 for t in self_w)),
-            "median_steps_cold": float(np.median([t if t >= 0 else H for t in self_c])),
-            "median_steps_warm": float(np.median([t if t >= 0 else H for t in self_w]))},
-        "runs_with_u_above_sqrt3_cs": int(sum(valid)),
-        "warm_vs_cold_late_phi_w_ratio_median": float(np.median(ref_w / ref)),
-        "median_steps_cold": float(np.median(steps_c)), "median_steps_warm": float(np.median(steps_w)),
-        "steps_saved_mean": float(np.mean(np.array(steps_c) - np.array(steps_w))),
-        "wall_potential_prediction_rel_err_median": float(np.median(np.abs(pred_phi - ref) / np.abs(ref))),
+        "batched_step_ms": el_c / H * 1e3, "plain_step_ms_mean": tau1 * 1e3,
         "train_loss_first_last": [losses[0], losses[-1]], "collect_seconds": t_col, "train_seconds": t_tr,
         "total_seconds": time.perf_counter() - t_all,
     }), flush=True)
@@ -827,8 +856,8 @@ def main() -> int:
     ap.add_argument("--plain-runs", type=int, default=32, help="runs timed one at a time in --steady")
     ap.add_argument("--max-steps", type=int, default=16384, help="step cap in --steady")
     ap.add_argument("--warm", action="store_true", help="learned warm start end to end, and exit")
-    ap.add_argument("--train-runs", type=int, default=512)
-    ap.add_argument("--eval-runs", type=int, default=128)
+    ap.add_argument("--train-runs", type=int, default=4096)
+    ap.add_argument("--eval-runs", type=int, default=512)
     ap.add_argument("--horizon", type=int, default=8192, help="steps per run in --warm")
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--only-2d", action="store_true", help="the 2D3V sheath line alone, and exit")

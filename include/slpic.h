@@ -114,13 +114,16 @@ typedef struct {
     double steady_tol;     /* steady when the last three window means of Phi_w  */
                            /* lie within steady_tol * |their mean| of it;       */
                            /* 0 = default 0.02                                  */
-    const double* warm_profile; /* NULL: cold load.  Else a host array of 5 x 256 */
+    const double* warm_profile; /* NULL: cold load.  Else a host array of 7 x 256 */
                            /* doubles on x/L = k/255 (k = 0..255): phi, n_e,    */
-                           /* n_i, Gamma_e, Gamma_i (physical), read by          */
-                           /* slpic_workspace_bytes and slpic_init only: each    */
-                           /* cell is loaded from the Maxwellian drifting at     */
-                           /* V = Gamma/n (|V| <= 4 vt) with n dx <1/beta>/w     */
-                           /* g-particles sampled as f/beta (Eq. 5)             */
+                           /* n_i, Gamma_e, Gamma_i, T_e, T_i (physical; T in   */
+                           /* T_e units, not positive = the species' source     */
+                           /* temperature), read by slpic_workspace_bytes and    */
+                           /* slpic_init only: each cell is loaded from the      */
+                           /* Maxwellian of its temperature (vt = sqrt(T/m))     */
+                           /* drifting at V = Gamma/n (|V| <= 4 vt) with         */
+                           /* n dx <1/beta>/w g-particles sampled as f/beta      */
+                           /* (Eq. 5)                                            */
     int32_t geometry;      /* SLPIC_GEOM_SHEATH (0), SLPIC_GEOM_PLATES or       */
                            /* SLPIC_GEOM_PERIODIC; the last two need no        */
                            /* warm_profile                                      */
@@ -352,20 +355,20 @@ int slpic_wave_push(int32_t precision, const slpic_wave_config* cfg, void* d_x, 
 const char* slpic_strerror(int code);
 
 /* ------------------------------------------------------------------------
- * Warm-start network (not in the paper): 4 -> 256 -> 256 -> 256 -> 1280,
+ * Warm-start network (not in the paper): 4 -> 256 -> 256 -> 256 -> 1792,
  * ReLU after the hidden layers, mapping standardised sheath parameters to
  * standardised steady profiles.  BF16 weights, biases, inputs and stored
  * activations (round to nearest even from FP32), FP32 accumulation on the
  * matrix cores.  Parameter vector, element offsets identical in the BF16
  * and the FP32 copy: W1 [256][4], b1 [256], W2 [256][256], b2 [256],
- * W3 [256][256], b3 [256], W4 [1280][256], b4 [1280].  The caller owns every
+ * W3 [256][256], b3 [256], W4 [1792][256], b4 [1792].  The caller owns every
  * buffer; batch must be a positive multiple of 16.  All calls are async on
  * stream and return SLPIC_EINVAL on bad arguments.
  * ------------------------------------------------------------------------ */
 #define SLPIC_MLP_IN 4
 #define SLPIC_MLP_HIDDEN 256
-#define SLPIC_MLP_OUT 1280
-#define SLPIC_MLP_PARAMS 461824
+#define SLPIC_MLP_OUT 1792
+#define SLPIC_MLP_PARAMS 593408
 
 /* Bytes of the activation buffer written by forward and read by backward
  * (BF16 inputs and the three hidden activations), and of backward's
@@ -376,7 +379,7 @@ size_t slpic_mlp_work_bytes(int32_t batch);
 /* d_params_bf16 (uint16 BF16 bits) = BF16 rounding of d_params_fp32. */
 int slpic_mlp_to_bf16(const float* d_params_fp32, void* d_params_bf16, void* stream);
 
-/* d_y [batch][1280] (FP32) from d_x [batch][4] (FP32); d_act receives the
+/* d_y [batch][1792] (FP32) from d_x [batch][4] (FP32); d_act receives the
  * activations backward needs. */
 int slpic_mlp_forward(const void* d_params_bf16, const float* d_x, float* d_y, int32_t batch, void* d_act,
                       void* stream);

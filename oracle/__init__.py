@@ -157,9 +157,10 @@ def lib():
             "orc_get_grid": (None, [_VP, _PD, _PD, _PD, _PD]),
             "orc_get_steady": (None, [_VP, ctypes.POINTER(_Steady)]),
             "orc_load_warm": (ctypes.c_int, [_VP, _PD]),
-            "orc_warm_cell_count": (_I64, [ctypes.POINTER(_Config), ctypes.c_int, _PD, ctypes.c_int32, _D, _PD]),
+            "orc_warm_cell_count": (_I64, [ctypes.POINTER(_Config), ctypes.c_int, _PD, ctypes.c_int32, _D, _PD, _PD]),
+            "orc_warm_cell_vt": (_D, [ctypes.POINTER(_Config), ctypes.c_int, _PD, ctypes.c_int32]),
             "orc_warm_particle": (None, [ctypes.POINTER(_Config), ctypes.c_int, ctypes.c_uint32, ctypes.c_int32, _D,
-                                         _PD]),
+                                         _D, _PD]),
             "orc_steady_init": (None, [ctypes.POINTER(_Steady), ctypes.c_int32, _D]),
             "orc_steady_feed": (None, [ctypes.POINTER(_Steady), _D, _I64]),
             "orc_wave_phi0": (_D, [ctypes.POINTER(_Wave), _D]),
@@ -243,19 +244,32 @@ def steady_detect(series, window: int, tol: float) -> dict:
     return d.as_dict()
 
 
+WARM_ROWS = 7  # phi, n_e, n_i, Gamma_e, Gamma_i, T_e, T_i
+
+
+def warm_profile(profile) -> np.ndarray:
+    """A (7, 256) contiguous warm-load profile; a (5, 256) one (no temperature
+    rows) gets zero temperature rows, which stand for the source temperatures."""
+    p = np.asarray(profile, dtype=np.float64)
+    if p.size == 5 * 256:
+        p = np.vstack([p.reshape(5, 256), np.zeros((2, 256))])
+    return np.ascontiguousarray(p.reshape(WARM_ROWS, 256))
+
+
 def warm_cell_count(cfg: dict, s: int, profile, c: int, w: float):
-    """(g-particle count, drift V) of cell c, species s, of a warm load."""
-    prof = np.ascontiguousarray(np.asarray(profile, dtype=np.float64).reshape(5, 256))
-    V = ctypes.c_double(0.0)
+    """(g-particle count, drift V, thermal speed vt) of cell c, species s, of a warm load."""
+    prof = warm_profile(profile)
+    V, vt = ctypes.c_double(0.0), ctypes.c_double(0.0)
     c_ = make_config(cfg)
-    n = lib().orc_warm_cell_count(ctypes.byref(c_), int(s), _dp(prof), int(c), float(w), ctypes.byref(V))
-    return int(n), V.value
+    n = lib().orc_warm_cell_count(ctypes.byref(c_), int(s), _dp(prof), int(c), float(w), ctypes.byref(V),
+                                  ctypes.byref(vt))
+    return int(n), V.value, vt.value
 
 
-def warm_particle(cfg: dict, s: int, i: int, c: int, V: float):
+def warm_particle(cfg: dict, s: int, i: int, c: int, V: float, vt: float):
     out = (ctypes.c_double * 4)()
     c_ = make_config(cfg)
-    lib().orc_warm_particle(ctypes.byref(c_), int(s), int(i) & 0xffffffff, int(c), float(V), out)
+    lib().orc_warm_particle(ctypes.byref(c_), int(s), int(i) & 0xffffffff, int(c), float(V), float(vt), out)
     return list(out)
 
 
@@ -382,15 +396,16 @@ class Run:
     """One 1D3V SLPIC run on the CPU (FP64)."""
 
     def __init__(self, cfg: dict, load: bool = True, warm=None):
-        """warm: optional (5, 256) profiles (phi, n_e, n_i, Gamma_e, Gamma_i on
-        x/L = k/255) for a warm load instead of the cold one."""
+        """warm: optional (7, 256) profiles (phi, n_e, n_i, Gamma_e, Gamma_i,
+        T_e, T_i on x/L = k/255; a (5, 256) one loads at the source
+        temperatures) for a warm load instead of the cold one."""
         self.cfg = dict(cfg)
         self._c = make_config(cfg)
         self._h = lib().orc_create(ctypes.byref(self._c))
         self.nx = self._c.nx
         self.nspecies = self._c.nspecies
         if warm is not None:
-            prof = np.ascontiguousarray(np.asarray(warm, dtype=np.float64).reshape(5, 256))
+            prof = warm_profile(warm)
             lib().orc_load_warm(self._h, _dp(prof))
         elif load:
             lib().orc_load(self._h)

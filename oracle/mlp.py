@@ -3,10 +3,10 @@
 The learned part is not in the paper: it is a small fully connected network
 that maps four sheath parameters (ln Te/Ti, ln A, u/v_ti, ln L/lambda_D,
 standardised) to steady profiles on 256 points of x/L (phi, n_e, n_i,
-Gamma_e, Gamma_i; 1280 outputs, standardised), so that a new run can be
-loaded near its steady state instead of cold.
+Gamma_e, Gamma_i, T_e, T_i; 1792 outputs, standardised), so that a new run
+can be loaded near its steady state instead of cold.
 
-Model: 4 -> 256 -> 256 -> 256 -> 1280, ReLU after the three hidden layers,
+Model: 4 -> 256 -> 256 -> 256 -> 1792, ReLU after the three hidden layers,
 mean squared error, Adam (beta1 0.9, beta2 0.999, eps 1e-8).  The GPU keeps
 weights, biases, inputs and stored activations in BF16 and accumulates in
 FP32; this oracle computes in FP64 and, with ``bf16=True``, rounds exactly
@@ -17,13 +17,13 @@ before they enter a product.
 
 Parameter vector (element offsets, the same in the BF16 and FP32 copies):
 W1 [256][4], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256],
-W4 [1280][256], b4 [1280]; 461,824 values.
+W4 [1792][256], b4 [1792]; 593,408 values.
 """
 from __future__ import annotations
 
 import numpy as np
 
-N_IN, N_HID, N_OUT = 4, 256, 1280
+N_IN, N_HID, N_OUT = 4, 256, 1792
 LAYERS = [(N_HID, N_IN), (N_HID, N_HID), (N_HID, N_HID), (N_OUT, N_HID)]
 
 
@@ -71,7 +71,7 @@ def init_params(seed: int) -> np.ndarray:
 
 
 def forward(params: np.ndarray, x: np.ndarray, bf16: bool = True):
-    """y [B][1280] and the cache (x, h1, h2, h3 as seen by the next layer)."""
+    """y [B][1792] and the cache (x, h1, h2, h3 as seen by the next layer)."""
     rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     p = {k: rnd(v) for k, v in unpack(params).items()}
     h = rnd(x)

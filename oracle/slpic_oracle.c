@@ -835,10 +835,12 @@ void orc_load(orc_run* r) {
 
 /* ------------------------------------------------------------------------ */
 /* Warm load from predicted steady profiles (a reading; the paper loads     */
-/* cold).  profile: 5 x 256 values on x/L = k/255: phi, n_e, n_i, Gamma_e,    */
-/* Gamma_i (physical).  In cell c (centre x/L = (c + 1/2)/nx), species s:    */
-/* n and Gamma by linear interpolation (n clamped at 0), drift              */
-/* V = Gamma/n clamped to |V| <= 4 vt, f = n Maxwellian(V e_x, vt) and       */
+/* cold).  profile: 7 x 256 values on x/L = k/255: phi, n_e, n_i, Gamma_e,    */
+/* Gamma_i, T_e, T_i (physical; T in T_e units).  In cell c (centre x/L =    */
+/* (c + 1/2)/nx), species s: n, Gamma and T by linear interpolation (n       */
+/* clamped at 0; T not positive: the species' source temperature), thermal  */
+/* speed vt = sqrt(T/m), drift V = Gamma/n clamped to |V| <= 4 vt,           */
+/* f = n Maxwellian(V e_x, vt) and                                          */
 /* g = f/beta (Eq. 5): the cell holds E = n dx Z / w g-particles, Z = <1/beta> */
 /* over the drifting Maxwellian, w the run's constant weight; the count is   */
 /* floor(E) + [U < frac(E)].  Positions uniform in the cell; velocities from */
@@ -895,9 +897,17 @@ static double interp_profile(const double* p, double xi) {
     return p[k] * (1.0 - f) + p[k + 1] * f;
 }
 
+/* The thermal speed of cell c of a warm load: sqrt(T/m) from the profile's
+ * temperature row of species s at the cell centre, or the species' own
+ * (source) temperature where that row is not positive. */
+double orc_warm_cell_vt(const orc_config* cfg, int s, const double* profile, int32_t c) {
+    double T = interp_profile(profile + 256 * (5 + s), ((double)c + 0.5) / (double)cfg->nx);
+    return T > 0.0 ? sqrt(T / cfg->species[s].mass) : species_vt(cfg, s);
+}
+
 int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile, int32_t c, double w,
-                            double* V_out) {
-    double vt = species_vt(cfg, s);
+                            double* V_out, double* vt_out) {
+    double vt = orc_warm_cell_vt(cfg, s, profile, c);
     double xi = ((double)c + 0.5) / (double)cfg->nx;
     const double* pn = profile + 256 * (s == 0 ? 1 : 2);
     const double* pg = profile + 256 * (s == 0 ? 3 : 4);
@@ -908,6 +918,7 @@ int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile,
     if (V > 4.0 * vt) V = 4.0 * vt;
     if (V < -4.0 * vt) V = -4.0 * vt;
     if (V_out) *V_out = V;
+    if (vt_out) *vt_out = vt;
     double E = n * cfg->dx * warm_Z(cfg->beta_kind, cfg->u, V, vt) / w;
     double fl = floor(E);
     orc_stream st;
@@ -915,10 +926,9 @@ int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile,
     return (int64_t)fl + (stream_next(&st) < E - fl ? 1 : 0);
 }
 
-void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double out[4]) {
+void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double vt, double out[4]) {
     orc_stream st;
     stream_init(&st, cfg, i, 0u, ORC_PURPOSE_WARM, s);
-    double vt = species_vt(cfg, s);
     double u = cfg->u;
     out[0] = (double)c + stream_next(&st);
     if (out[0] >= (double)(c + 1)) out[0] = nextafter((double)(c + 1), 0.0);
@@ -941,12 +951,12 @@ int orc_load_warm(orc_run* r, const double* profile) {
     for (int s = 0; s < r->cfg.nspecies; ++s) {
         int64_t i = 0;
         for (int32_t c = 0; c < r->cfg.nx; ++c) {
-            double V;
-            int64_t cnt = orc_warm_cell_count(&r->cfg, s, profile, c, r->w[s], &V);
+            double V, vt;
+            int64_t cnt = orc_warm_cell_count(&r->cfg, s, profile, c, r->w[s], &V, &vt);
             ensure_capacity(r, s, i + cnt);
             for (int64_t k = 0; k < cnt; ++k, ++i) {
                 double p[4];
-                orc_warm_particle(&r->cfg, s, (uint32_t)i, c, V, p);
+                orc_warm_particle(&r->cfg, s, (uint32_t)i, c, V, vt, p);
                 r->x[s][i] = p[0]; r->vx[s][i] = p[1]; r->vy[s][i] = p[2]; r->vz[s][i] = p[3];
             }
         }

@@ -132,12 +132,14 @@ void orc_load(orc_run* r);
 void orc_refresh_fields(orc_run* r);
 void orc_step(orc_run* r, int32_t nsteps);
 /* Warm load (replaces the particles, resets the counters, sorts if sorting
- * is on and refreshes the fields): profile = 5 x 256 doubles on x/L = k/255,
- * phi, n_e, n_i, Gamma_e, Gamma_i. */
+ * is on and refreshes the fields): profile = 7 x 256 doubles on x/L = k/255,
+ * phi, n_e, n_i, Gamma_e, Gamma_i, T_e, T_i (a temperature not positive
+ * stands for the species' source temperature). */
 int orc_load_warm(orc_run* r, const double* profile);
+double orc_warm_cell_vt(const orc_config* cfg, int s, const double* profile, int32_t c);
 int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile, int32_t c, double w,
-                            double* V_out);
-void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double out[4]);
+                            double* V_out, double* vt_out);
+void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double vt, double out[4]);
 void orc_sort(orc_run* r, int32_t* perm0, int32_t* perm1);
 void orc_keys(const orc_run* r, int32_t s, int32_t* keys);
 void orc_moments(const orc_run* r, double* out);

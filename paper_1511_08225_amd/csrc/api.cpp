@@ -96,10 +96,12 @@ static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, in
                                  std::vector<WarmCell>& out) {
     const double* pn = c.warm_profile + 256 * (s == 0 ? 1 : 2);
     const double* pg = c.warm_profile + 256 * (s == 0 ? 3 : 4);
-    const double vt = R.vt[s];
+    const double* pT = c.warm_profile + 256 * (5 + s);
     int64_t start = 0;
     for (int cell = 0; cell < c.nx; ++cell) {
         const double xi = ((double)cell + 0.5) / (double)c.nx;
+        const double T = profile_at(pT, xi);  // not positive: the source temperature
+        const double vt = T > 0.0 ? std::sqrt(T / R.mass[s]) : R.vt[s];
         double n = profile_at(pn, xi);
         if (!(n > 0.0)) n = 0.0;
         const double G = profile_at(pg, xi);
@@ -110,7 +112,7 @@ static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, in
         const U4 r = philox10((uint32_t)cell, 0u, R.run_id, ((uint32_t)kPurposeWarmCount << 24) | ((uint32_t)s << 20),
                               R.seed_lo, R.seed_hi);
         const int64_t cnt = (int64_t)fl + (u53(r.v[0], r.v[1]) < E - fl ? 1 : 0);
-        if (cnt > 0) out.push_back(WarmCell{run, s, cell, (int32_t)cnt, start, V});
+        if (cnt > 0) out.push_back(WarmCell{run, s, cell, (int32_t)cnt, start, V, vt});
         start += cnt;
     }
     return start;

@@ -1,4 +1,4 @@
-// mlp.hip -- the warm-start network on gfx950: 4 -> 256 -> 256 -> 256 -> 1280,
+// mlp.hip -- the warm-start network on gfx950: 4 -> 256 -> 256 -> 256 -> 1792,
 // ReLU after the hidden layers.  Weights, biases, inputs and stored
 // activations are BF16 (round to nearest even from FP32); products
 // accumulate in FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16), one
@@ -8,7 +8,7 @@
 //
 // Parameter vector (element offsets, identical in the BF16 and FP32 copies):
 // W1 [256][4], b1 [256], W2 [256][256], b2, W3 [256][256], b3,
-// W4 [1280][256], b4 [1280].
+// W4 [1792][256], b4 [1792].
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -99,11 +99,12 @@ __host__ __device__ inline bool retired(const RunInfo& R, const RunState& st) {
 }
 
 // One cell of a warm load: `count` particles of (run, species) at slots
-// start.., drawn from a Maxwellian drifting at V along x, as f/beta.
+// start.., drawn from a Maxwellian of thermal speed vt drifting at V along x,
+// as f/beta.
 struct WarmCell {
     int32_t run, species, cell, count;
     int64_t start;
-    double V;
+    double V, vt;
 };
 
 // A contiguous slot range of one (run, species): one push / load / moments

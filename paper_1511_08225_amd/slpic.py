@@ -254,9 +254,10 @@ class Sim:
 
     def __init__(self, configs, precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0,
                  graph_steps=0, sort_tile=0, device="cuda", warm=None, retire_steady=False, push_order=0):
-        """warm: optional list (one entry per run) of None or a (5, 256)
-        array of predicted profiles (phi, n_e, n_i, Gamma_e, Gamma_i on
-        x/L = k/255) for a warm load instead of the cold one."""
+        """warm: optional list (one entry per run) of None or a (7, 256)
+        array of predicted profiles (phi, n_e, n_i, Gamma_e, Gamma_i, T_e,
+        T_i on x/L = k/255; a (5, 256) array loads at the source
+        temperatures) for a warm load instead of the cold one."""
         if isinstance(configs, dict):
             configs = [configs]
         self.configs = [dict(c) for c in configs]
@@ -270,7 +271,10 @@ class Sim:
             for r, prof in enumerate(warm):
                 if prof is None:
                     continue
-                a = np.ascontiguousarray(np.asarray(prof, dtype=np.float64).reshape(5, 256))
+                a = np.asarray(prof, dtype=np.float64)
+                if a.size == 5 * 256:  # no temperature rows: the source temperatures
+                    a = np.vstack([a.reshape(5, 256), np.zeros((2, 256))])
+                a = np.ascontiguousarray(a.reshape(7, 256))
                 self._warm.append(a)
                 self._cfg[r].warm_profile = a.ctypes.data
         self._tun = tuning(precision, sort_every, sort_bucket, chunk, block, graph_steps, sort_tile, retire_steady,
@@ -438,7 +442,7 @@ def fixed_point_round(xt: np.ndarray, fixed_bits: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- warm-start network
-MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 4, 256, 1280, 461824
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 4, 256, 1792, 593408
 MLP_NOALLOC_MAX_BATCH = 1024
 
 
@@ -470,7 +474,7 @@ class Mlp:
         return _P(torch.cuda.current_stream(self.device).cuda_stream)
 
     def forward(self, x) -> torch.Tensor:
-        """y [batch][1280] from x [batch][4] (FP32, standardised)."""
+        """y [batch][1792] from x [batch][4] (FP32, standardised)."""
         x = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
         if tuple(x.shape) != (self.batch, MLP_IN):
             raise SlpicError("x must be [batch][4]")
@@ -482,7 +486,7 @@ class Mlp:
     def forward_noalloc(self, x, y=None) -> torch.Tensor:
         """The same forward pass through slpic_mlp_forward_noalloc: the
         activations stay in the library's fixed device array (nothing for
-        backward); y [n][1280] is written for x [n][4], n a multiple of 16 up
+        backward); y [n][1792] is written for x [n][4], n a multiple of 16 up
         to MLP_NOALLOC_MAX_BATCH."""
         x = torch.as_tensor(x, dtype=torch.float32).to(self.device).contiguous()
         if x.dim() != 2 or x.shape[1] != MLP_IN:

@@ -73,29 +73,36 @@ def test_cold_load_matches_oracle(gpu_lib):
             sim.close()
 
 
-def _warm_profile(nx_phys_scale=1.0):
+def _warm_profile(nx_phys_scale=1.0, hot=False):
+    """phi, n_e, n_i, Gamma_e, Gamma_i, and (hot) temperature rows T_e from 1
+    to 3 T_e, T_i from 1 to 1.5 times the source's (zero rows: the source
+    temperatures)."""
     xi = np.arange(256) / 255.0
-    p = np.zeros((5, 256))
+    p = np.zeros((7, 256))
     p[0] = 5.0 * (1 - xi ** 2)
     p[1] = 1.0 + 0.5 * np.cos(math.pi * xi)
     p[2] = p[1] * (1.0 + 0.05 * xi)
     p[3] = p[1] * 0.2 * xi
     p[4] = p[2] * 0.004 * xi * nx_phys_scale
+    if hot:
+        p[5] = 1.0 + 2.0 * xi
+        p[6] = 0.05 * (1.0 + 0.5 * xi)
     return p
 
 
-def test_warm_load_matches_oracle(gpu_lib):
-    """Warm load from a smooth profile (density, drifts): per-cell counts and
-    positions as in the oracle, velocities to 1e-12 but for a few rejection
-    flips from last-bit libm differences; a cold run beside it in the same
-    context is unaffected."""
-    prof = _warm_profile()
+@pytest.mark.parametrize("hot", [False, True])
+def test_warm_load_matches_oracle(gpu_lib, hot):
+    """Warm load from a smooth profile (density, drifts, and with hot = True
+    a temperature per cell): per-cell counts and positions as in the oracle,
+    velocities to 1e-12 but for a few rejection flips from last-bit libm
+    differences; a cold run beside it in the same context is unaffected."""
+    prof = _warm_profile(hot=hot)
     for prec in ("f64", "f32"):
         for kind, k in (("step", 3.0), ("smooth", 3.0), ("step", math.inf)):
             cfg = workloads.sheath(nx=64, ppc=100, u_over_vti=k, dt=5.0 if k < 1e9 else 0.1,
                                    beta_kind=kind, sort_every=0, seed=12)
             cold = dict(cfg, run=1, seed=13)
-            print_case(f"warm load {prec} {kind} u/vti={k}")
+            print_case(f"warm load {prec} {kind} u/vti={k} hot={hot}")
             sim = gpu_lib.Sim([cfg, cold], precision=prec, sort_every=0, warm=[prof, None])
             run = oracle.Run(cfg, warm=prof)
             run_cold = oracle.Run(cold)

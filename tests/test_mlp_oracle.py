@@ -9,7 +9,7 @@ from oracle import mlp
 
 
 def test_layout_counts():
-    assert mlp.N_PARAMS == 461824
+    assert mlp.N_PARAMS == 593408
     names = [n for n, _, _ in mlp.layout()]
     assert names == ["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"]
     v = np.arange(mlp.N_PARAMS, dtype=np.float64)

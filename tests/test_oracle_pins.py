@@ -608,8 +608,14 @@ def test_warm_load_uniform_profile_reproduces_cold_counts():
         w = oracle.Run(cfg, load=False).weights()
         for s in range(2):
             for c in (0, 7, 15):
-                cnt, V = oracle.warm_cell_count(cfg, s, _uniform_profile(), c, w[s])
+                cnt, V, vt = oracle.warm_cell_count(cfg, s, _uniform_profile(), c, w[s])
                 assert cnt == 50 and V == 0.0, (kind, s, c, cnt)
+                # zero temperature rows stand for the source temperature
+                T0 = cfg["species"][s]["temperature"]
+                assert vt == math.sqrt(T0 / cfg["species"][s]["mass"])
+                hot = oracle.warm_profile(_uniform_profile())
+                hot[5 + s] = T0
+                assert oracle.warm_cell_count(cfg, s, hot, c, w[s]) == (cnt, V, vt)
 
 
 def test_warm_Z_with_drift_against_cylindrical_quadrature():
@@ -621,32 +627,41 @@ def test_warm_Z_with_drift_against_cylindrical_quadrature():
     w = run.weights()
     vt = math.sqrt(cfg["species"][1]["temperature"] / cfg["species"][1]["mass"])
     u = cfg["u"]
-    for V_over_vt in (0.0, 0.7, 2.5):
+    vt0 = vt
+    for V_over_vt, T_scale in ((0.0, 1.0), (0.7, 1.0), (2.5, 1.0), (0.7, 4.0), (1.5, 0.25)):
+        vt = vt0 * math.sqrt(T_scale)  # a temperature row T_scale T_i moves the thermal speed
         V = V_over_vt * vt
-        prof = _uniform_profile(n=0.8, gamma=0.8 * V)
+        prof = oracle.warm_profile(_uniform_profile(n=0.8, gamma=0.8 * V))
+        if T_scale != 1.0:
+            prof[6] = T_scale * cfg["species"][1]["temperature"]
         inv_beta = lambda sp: 1.0 if sp <= u else sp / u
         dens = lambda r, a: (math.exp(-(a - V) ** 2 / (2 * vt * vt)) / (vt * math.sqrt(2 * math.pi))
                              * r / (vt * vt) * math.exp(-r * r / (2 * vt * vt)))
         Z, _ = integrate.dblquad(lambda r, a: inv_beta(math.hypot(a, r)) * dens(r, a),
                                  V - 12 * vt, V + 12 * vt, 0.0, 12 * vt, epsabs=1e-12, epsrel=1e-11)
         E = 0.8 * cfg["dx"] * Z / w[1]
-        cnt, Vo = oracle.warm_cell_count(cfg, 1, prof, 5, w[1])
+        cnt, Vo, vto = oracle.warm_cell_count(cfg, 1, prof, 5, w[1])
         assert Vo == pytest.approx(V, rel=1e-12, abs=1e-300)
-        assert cnt in (math.floor(E), math.floor(E) + 1), (V_over_vt, cnt, E)
+        assert vto == pytest.approx(vt, rel=1e-14)
+        assert cnt in (math.floor(E), math.floor(E) + 1), (V_over_vt, T_scale, cnt, E)
 
 
 def test_warm_load_reproduces_profile_moments():
     """The physical moments of a warm-loaded state (f = beta g, Eq. 5) match
-    the profile it was drawn from: density and flux within statistics."""
+    the profile it was drawn from: density and flux within statistics, and
+    the temperature (2K/n - m V^2)/3 from the kinetic energy density K."""
     cfg = workloads.sheath(nx=32, ppc=2000, u_over_vti=3.0, dt=5.0, sort_every=1)
     xi = np.arange(256) / 255.0
     vte = 1.0
-    vti = math.sqrt(cfg["species"][1]["temperature"] / cfg["species"][1]["mass"])
-    prof = np.zeros((5, 256))
+    Ti0 = cfg["species"][1]["temperature"]
+    vti = math.sqrt(Ti0 / cfg["species"][1]["mass"])
+    prof = np.zeros((7, 256))
     prof[1] = 1.0 + 0.5 * np.cos(math.pi * xi)     # n_e
     prof[2] = prof[1]                              # n_i
     prof[3] = prof[1] * 0.3 * vte * xi             # Gamma_e: drift 0.3 v_te at the wall
     prof[4] = prof[2] * 1.5 * vti * xi             # Gamma_i: drift 1.5 v_ti at the wall
+    prof[5] = 1.0 + 3.0 * xi                       # T_e: 1 to 4 T_e
+    prof[6] = Ti0 * (2.0 - xi)                     # T_i: 2 to 1 T_i
     run = oracle.Run(cfg, warm=prof)
     M = run.moments()
     nodes = np.arange(cfg["nx"] + 1) / cfg["nx"]
@@ -661,3 +676,9 @@ def test_warm_load_reproduces_profile_moments():
         # w u of it): compare its average over the inner nodes
         avg_got, avg_want = g_got[inner].mean(), g_want[inner].mean()
         assert avg_got == pytest.approx(avg_want, rel=0.08), (s, avg_got, avg_want)
+        m = cfg["species"][s]["mass"]
+        K = M[grow]
+        T_got = (2.0 * K / n_got - m * (g_got / n_got) ** 2) / 3.0
+        T_want = np.interp(nodes, xi, prof[5 + s])
+        relT = np.abs(T_got[inner] - T_want[inner]) / T_want[inner]
+        assert relT.mean() < 0.03 and relT.max() < 0.1, (s, relT.mean(), relT.max())

@@ -56,7 +56,7 @@ def test_noalloc_forward_equals_forward_on_two_calls(gpu_lib):
     # one batch step beyond it: rejected before any launch
     n = gpu_lib.MLP_NOALLOC_MAX_BATCH + 16
     xo = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
-    yo = torch.zeros((n, 1280), dtype=torch.float32, device="cuda")
+    yo = torch.zeros((n, gpu_lib.MLP_OUT), dtype=torch.float32, device="cuda")
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     rc = L.slpic_mlp_forward_noalloc(ctypes.c_void_p(net2.pbf16.data_ptr()), ctypes.c_void_p(xo.data_ptr()),
                                      ctypes.c_void_p(yo.data_ptr()), n, stream)
