@@ -53,7 +53,8 @@ class _Config(ctypes.Structure):
                 ("kick", ctypes.c_int32), ("mmp_tol", ctypes.c_double),
                 ("capacity_factor", ctypes.c_double), ("steady_window", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("steady_tol", ctypes.c_double), ("geometry", ctypes.c_int32),
-                ("pad2", ctypes.c_int32), ("bias", ctypes.c_double)]
+                ("pad2", ctypes.c_int32), ("bias", ctypes.c_double),
+                ("limit", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Steady(ctypes.Structure):
@@ -231,6 +232,13 @@ def make_config(cfg: dict) -> _Config:
     c.steady_tol = float(cfg.get("steady_tol", 0.0))
     c.geometry = {"sheath": GEOM_SHEATH, "plates": GEOM_PLATES, "periodic": GEOM_PERIODIC}[cfg.get("geometry", "sheath")]
     c.bias = float(cfg.get("bias", 0.0))
+    prof = cfg.get("limit_profile")
+    if prof is not None:  # nx + 1 node values of a speed limit varying with position
+        a = np.ascontiguousarray(np.asarray(prof, dtype=np.float64).reshape(-1))
+        if a.size != c.nx + 1:
+            raise ValueError("limit_profile needs nx + 1 node values")
+        c._limit = a  # kept alive with the struct
+        c.limit = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return c
 
 
@@ -402,6 +410,8 @@ class Run:
         self.cfg = dict(cfg)
         self._c = make_config(cfg)
         self._h = lib().orc_create(ctypes.byref(self._c))
+        if not self._h:
+            raise ValueError("invalid run configuration")
         self.nx = self._c.nx
         self.nspecies = self._c.nspecies
         if warm is not None:
@@ -456,7 +466,7 @@ class Run:
         f = beta g is kept at the weight of a fresh load at u, set dt,
         recompute the fields."""
         if lib().orc_set_speed_limit(self._h, float(u), float(dt)) != 0:
-            raise ValueError("speed limit may only rise, dt must be positive")
+            raise ValueError("the limit and dt must be positive; a run with a limit profile keeps it")
         self.cfg["u"], self.cfg["dt"] = float(u), float(dt)
 
     def weight(self, s: int) -> float:
@@ -555,6 +565,8 @@ class Run2D:
         self._c = make_config(cfg)
         self.nx, self.ny, self.tile = self._c.nx, int(ny), int(tile)
         self._h = lib().orc2_create(ctypes.byref(self._c), self.ny, self.tile)
+        if not self._h:
+            raise ValueError("invalid run configuration")
         if load:
             lib().orc2_load(self._h)
 

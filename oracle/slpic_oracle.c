@@ -628,7 +628,8 @@ double orc_wall_flux_per_step(const orc_config* cfg, int s) {
 /* Particle k entering through the plate at x = L in step `step`: v_x from
  * the flux-weighted half Maxwellian (v_x = -v_t sqrt(-2 ln(1 - U))), v_y, v_z
  * Maxwellian, and a position a uniform fraction of this step's travel
- * beta(|v|) |v_x| dt inside the plate (held within source_cells). */
+ * beta(|v|) |v_x| dt inside the plate (held within source_cells; beta with
+ * the limit at the plate). */
 void orc_wall_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t step, double out[4]) {
     orc_stream st;
     stream_init(&st, cfg, k, step, ORC_PURPOSE_WALL, s);
@@ -638,7 +639,8 @@ void orc_wall_inject_particle(const orc_config* cfg, int s, uint32_t k, uint32_t
     stream_normal3(&st, z);
     double vy = vt * z[0], vz = vt * z[1];
     double s2 = vx * vx + (vy * vy + vz * vz);
-    double depth = beta_of_s2(cfg->beta_kind, cfg->u, s2) * fabs(vx) * cfg->dt / cfg->dx * stream_next(&st);
+    double ul = cfg->limit ? cfg->limit[cfg->nx] : cfg->u;
+    double depth = beta_of_s2(cfg->beta_kind, ul, s2) * fabs(vx) * cfg->dt / cfg->dx * stream_next(&st);
     if (depth > (double)cfg->source_cells) depth = (double)cfg->source_cells;
     double x = (double)cfg->nx - depth;
     if (x >= (double)cfg->nx) x = nextafter((double)cfg->nx, 0.0);
@@ -681,6 +683,7 @@ void orc_steady_feed(orc_steady* d, double phi_w, int64_t step_count) {
 struct orc_run {
     orc_steady steady;
     orc_config cfg;
+    double* U;  /* nodes of a position-dependent speed limit (NULL: uniform) */
     double w[2], qw[2], qm[2], vt[2];
     int64_t n[2], cap[2];
     double *x[2], *vx[2], *vy[2], *vz[2];
@@ -702,9 +705,35 @@ static void ensure_capacity(orc_run* r, int s, int64_t need) {
     r->cap[s] = cap;
 }
 
+/* The speed limit at position xt (grid units) of a run: the node values of
+ * its limit profile interpolated linearly, or the uniform limit u. */
+static double run_limit(const orc_run* r, double xt) {
+    if (!r->U) return r->cfg.u;
+    int c = (int)floor(xt);
+    if (c < 0) c = 0;
+    if (c > r->cfg.nx - 1) c = r->cfg.nx - 1;
+    double f = xt - (double)c;
+    return r->U[c] * (1.0 - f) + r->U[c + 1] * f;
+}
+
+/* The speed limit at the centre of cell c of a configuration (the loaders). */
+static double cell_limit(const orc_config* cfg, int32_t c) {
+    return cfg->limit ? 0.5 * (cfg->limit[c] + cfg->limit[c + 1]) : cfg->u;
+}
+
 orc_run* orc_create(const orc_config* cfg) {
+    if (cfg->limit) {  /* finite positive nodes */
+        if (!isfinite(cfg->u)) return NULL;
+        for (int j = 0; j <= cfg->nx; ++j)
+            if (!(cfg->limit[j] > 0.0) || !isfinite(cfg->limit[j])) return NULL;
+    }
     orc_run* r = (orc_run*)calloc(1, sizeof(orc_run));
     r->cfg = *cfg;
+    if (cfg->limit) {  /* the run keeps its own copy of the limit profile */
+        r->U = (double*)malloc(sizeof(double) * (size_t)(cfg->nx + 1));
+        memcpy(r->U, cfg->limit, sizeof(double) * (size_t)(cfg->nx + 1));
+        r->cfg.limit = r->U;
+    }
     orc_steady_init(&r->steady, cfg->steady_window > 0 ? cfg->steady_window : (cfg->nx / 4 > 1 ? cfg->nx / 4 : 1),
                     cfg->steady_tol > 0.0 ? cfg->steady_tol : 0.02);
     int nodes = cfg->nx + 1;
@@ -730,10 +759,12 @@ void orc_destroy(orc_run* r) {
     }
     free(r->phi);
     free(r->E);
+    free(r->U);
     free(r);
 }
 
-/* Eq. (A2c): Q_j = sum_p q w beta(|v^{n+1/2}|) W_j(x^{n+1}) with CIC W. */
+/* Eq. (A2c): Q_j = sum_p q w beta(|v^{n+1/2}|) W_j(x^{n+1}) with CIC W (a
+ * limit varying with position: beta with the limit at x^{n+1}). */
 static void deposit(orc_run* r) {
     int nodes = r->cfg.nx + 1;
     for (int s = 0; s < r->cfg.nspecies; ++s) {
@@ -742,7 +773,7 @@ static void deposit(orc_run* r) {
             double xt = r->x[s][i];
             if (xt < 0.0) continue;
             double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
-            double b = beta_of_s2(r->cfg.beta_kind, r->cfg.u, norm2(v));
+            double b = beta_of_s2(r->cfg.beta_kind, run_limit(r, xt), norm2(v));
             int c = (int)floor(xt);
             double f = xt - (double)c;
             double wb = r->qw[s] * b;
@@ -815,7 +846,17 @@ void orc_sort(orc_run* r, int32_t* perm0, int32_t* perm1) {
     }
 }
 
+static int load_cells(orc_run* r, const double* profile);
+
 void orc_load(orc_run* r) {
+    if (r->U && r->cfg.geometry != ORC_GEOM_PLATES) {
+        /* g0 = f0/beta with the limit of each cell: cell by cell, at n0 = 1 and rest */
+        double* uni = (double*)calloc(7 * 256, sizeof(double));
+        for (int k = 0; k < 256; ++k) uni[256 + k] = uni[512 + k] = 1.0;
+        load_cells(r, uni);
+        free(uni);
+        return;
+    }
     for (int s = 0; s < r->cfg.nspecies; ++s) {
         int64_t n0 = r->cfg.geometry == ORC_GEOM_PLATES ? 0 : (int64_t)r->cfg.nx * r->cfg.species[s].ppc;
         ensure_capacity(r, s, n0);
@@ -919,7 +960,7 @@ int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile,
     if (V < -4.0 * vt) V = -4.0 * vt;
     if (V_out) *V_out = V;
     if (vt_out) *vt_out = vt;
-    double E = n * cfg->dx * warm_Z(cfg->beta_kind, cfg->u, V, vt) / w;
+    double E = n * cfg->dx * warm_Z(cfg->beta_kind, cell_limit(cfg, c), V, vt) / w;
     double fl = floor(E);
     orc_stream st;
     stream_init(&st, cfg, (uint32_t)c, 0u, ORC_PURPOSE_WARM_COUNT, s);
@@ -929,7 +970,7 @@ int64_t orc_warm_cell_count(const orc_config* cfg, int s, const double* profile,
 void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, double V, double vt, double out[4]) {
     orc_stream st;
     stream_init(&st, cfg, i, 0u, ORC_PURPOSE_WARM, s);
-    double u = cfg->u;
+    double u = cell_limit(cfg, c);
     out[0] = (double)c + stream_next(&st);
     if (out[0] >= (double)(c + 1)) out[0] = nextafter((double)(c + 1), 0.0);
     double M = inv_beta(cfg->beta_kind, u, fabs(V) + 8.0 * vt);
@@ -947,7 +988,9 @@ void orc_warm_particle(const orc_config* cfg, int s, uint32_t i, int32_t c, doub
     out[1] = v[0]; out[2] = v[1]; out[3] = v[2];
 }
 
-int orc_load_warm(orc_run* r, const double* profile) {
+int orc_load_warm(orc_run* r, const double* profile) { return load_cells(r, profile); }
+
+static int load_cells(orc_run* r, const double* profile) {
     for (int s = 0; s < r->cfg.nspecies; ++s) {
         int64_t i = 0;
         for (int32_t c = 0; c < r->cfg.nx; ++c) {
@@ -1004,13 +1047,16 @@ double orc_run_weight(const orc_run* r, int32_t s) { return r->w[s]; }
  * the new limit, w' = dx Z(u')/ppc, and each live g-particle of velocity v,
  * in slot order, is replaced by m copies, m = floor(p) + [U < p - floor(p)]
  * with p = (beta_u(|v|) w) / (beta_u'(|v|) w'), so that the expected
- * beta' w' g' equals beta w g at every velocity (a raise only: then beta'
- * >= beta and p <= w/w', at most 255 copies).  U is the first draw of the
- * particle's own stream (purpose 6, its slot index, the current step).
- * Then dt becomes dt' and the charge and fields are recomputed. */
+ * beta' w' g' equals beta w g at every velocity.  A raise has beta' >= beta
+ * and p <= w/w'; a lowering has p <= (beta/beta') (w/w'), a ratio of order
+ * |v| / <|v|> for the fast particles, and the slow ones (beta' = beta) are
+ * thinned by w/w' < 1.  m is capped at 255 copies.  U is the first draw of
+ * the particle's own stream (purpose 6, its slot index, the current step).
+ * Then dt becomes dt' and the charge and fields are recomputed.  A run with
+ * a limit profile keeps it (-1). */
 int orc_set_speed_limit(orc_run* r, double u_new, double dt_new) {
     orc_config nc = r->cfg;
-    if (!(u_new >= r->cfg.u) || !(dt_new > 0.0)) return -1;
+    if (!(u_new > 0.0) || !(dt_new > 0.0) || r->U) return -1;
     nc.u = u_new;
     nc.dt = dt_new;
     for (int s = 0; s < r->cfg.nspecies; ++s) {
@@ -1071,12 +1117,14 @@ void orc_step(orc_run* r, int32_t nsteps) {
                 double a[3] = {r->qm[s] * Ex, 0.0, 0.0};
                 double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
                 double v1[3];
+                /* the speed limit of the step: at x^n, frozen like E^n(x^n) */
+                double up = run_limit(r, xt);
                 if (cfg->kick == ORC_KICK_MMP)
-                    orc_kick_mmp(cfg->beta_kind, cfg->u, cfg->dt, v, a, cfg->mmp_tol, 1 << 20, v1);
+                    orc_kick_mmp(cfg->beta_kind, up, cfg->dt, v, a, cfg->mmp_tol, 1 << 20, v1);
                 else
-                    orc_kick_exact(cfg->beta_kind, cfg->u, cfg->dt, v, a, v1);
+                    orc_kick_exact(cfg->beta_kind, up, cfg->dt, v, a, v1);
                 /* Eq. (A2b): x^{n+1} = x^n + beta(|v^{n+1/2}|) v^{n+1/2} dt */
-                double b = beta_of_s2(cfg->beta_kind, cfg->u, norm2(v1));
+                double b = beta_of_s2(cfg->beta_kind, up, norm2(v1));
                 double xn = xt + b * v1[0] * dtdx;
                 int left_out = 0;
                 if (cfg->geometry == ORC_GEOM_PERIODIC) {
@@ -1151,7 +1199,7 @@ void orc_moments(const orc_run* r, double* out) {
             if (xt < 0.0) continue;
             double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
             double v2 = norm2(v);
-            double wb = r->w[s] * beta_of_s2(r->cfg.beta_kind, r->cfg.u, v2);
+            double wb = r->w[s] * beta_of_s2(r->cfg.beta_kind, run_limit(r, xt), v2);
             int c = (int)floor(xt);
             double f = xt - (double)c;
             double w0 = wb * (1.0 - f), w1 = wb * f;
@@ -1243,6 +1291,7 @@ static void ensure2(orc2_run* r, int s, int64_t need) {
 }
 
 orc2_run* orc2_create(const orc_config* cfg, int32_t ny, int32_t tile) {
+    if (cfg->limit) return NULL;  /* 2D runs take one uniform limit */
     orc2_run* r = (orc2_run*)calloc(1, sizeof(orc2_run));
     r->cfg = *cfg;
     r->ny = ny;

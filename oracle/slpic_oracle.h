@@ -66,6 +66,10 @@ typedef struct {
     int32_t geometry;      /* ORC_GEOM_SHEATH / ORC_GEOM_PLATES / ORC_GEOM_PERIODIC */
     int32_t pad2;
     double bias;           /* plates: phi(L) in T_e/e                         */
+    const double* limit;   /* NULL: the speed limit is u everywhere.  Else nx+1 */
+                           /* node values of a limit varying with position:    */
+                           /* v0(x) linear between nodes (u then only sets the  */
+                           /* species weights, w = dx Z(u)/ppc)                 */
 } orc_config;
 
 /* Steady-state detector on the wall potential (a reading: the paper calls
@@ -126,6 +130,14 @@ double orc_slpic_plasma_freq2(int kind, double u, double vt);
 double orc_slpic_dispersion(int kind, double u, double vt, double k);
 
 /* --- run ----------------------------------------------------------------- */
+/* A run of cfg.  With a limit profile (cfg->limit, copied): the step takes
+ * the limit at x^n for the velocity map and the move, frozen over the step
+ * like E^n(x^n); the deposit and the moments take it at the particle's
+ * position, the plates' wall source the limit at the plate; orc_load loads
+ * cell by cell (unit density at rest, each cell's g-particles sampled as
+ * f/beta at the limit of its centre, the mean of its two nodes) through the
+ * warm loader (plates: nothing).  NULL for a profile node that is not finite
+ * and positive, or an infinite u. */
 orc_run* orc_create(const orc_config* cfg);
 void orc_destroy(orc_run* r);
 void orc_load(orc_run* r);
@@ -157,10 +169,10 @@ int orc_set_particles(orc_run* r, int32_t s, int64_t n, const double* x, const d
 void orc_set_counters(orc_run* r, int64_t step, double acc_e);
 /* Plates: the fractional wall injection carried over, per species. */
 double orc_acc_flux(const orc_run* r, int32_t s);
-/* A higher speed limit mid-run (u_new >= the current u; dt_new > 0): f =
+/* A new speed limit mid-run, higher or lower (u_new > 0, dt_new > 0): f =
  * beta g is kept by resampling the g-particles at the weight of a fresh
  * load at u_new; then the fields are recomputed.  Returns 0, or -1 for an
- * invalid argument. */
+ * invalid argument or a run with a limit profile. */
 int orc_set_speed_limit(orc_run* r, double u_new, double dt_new);
 /* The current macroparticle weight of species s. */
 double orc_run_weight(const orc_run* r, int32_t s);

@@ -1,9 +1,9 @@
-"""Pins of the oracle's mid-run rise of the speed limit (the limit may vary
-in time): the resampling keeps f = beta g.  A uniform box loaded as
+"""Pins of the oracle's mid-run change of the speed limit (the limit may
+vary in time): the resampling keeps f = beta g.  A uniform box loaded as
 g0 = f0/beta at one limit and raised to u = inf must hold a Maxwellian (the
-PIC distribution); raised to another finite limit, the same distribution as
-a fresh load there; the beta-weighted charge is kept within its sampling
-noise; an unchanged limit changes nothing."""
+PIC distribution); raised or lowered to another finite limit, the same
+distribution as a fresh load there; the beta-weighted charge is kept within
+its sampling noise; an unchanged limit changes nothing."""
 import math
 
 import numpy as np
@@ -33,8 +33,9 @@ def test_same_limit_is_identity():
         for a, b in zip(before[s], run.particles(s)):
             assert np.array_equal(a, b)
         assert run.weight(s) == w[s]
-    with pytest.raises(ValueError):
-        run.set_speed_limit(0.25, cfg["dt"])  # lowering is not a rise
+    for bad in ((0.0, cfg["dt"]), (-1.0, cfg["dt"]), (0.25, 0.0)):
+        with pytest.raises(ValueError):
+            run.set_speed_limit(*bad)
 
 
 def test_raise_to_pic_gives_maxwellian():
@@ -80,3 +81,48 @@ def test_charge_kept_within_noise():
         c = abs(q1[s]).sum() / max(run.nslots(s), 1)
         sigma = c * math.sqrt(run.nslots(s)) / 2.0
         assert abs(tot1 - tot0) <= 5 * sigma + 1e-12 * abs(tot0), (s, tot0, tot1, sigma)
+
+
+def test_lower_matches_fresh_load():
+    """From u = 1.0 down to u = 0.3 v_te: the resampled electron speeds and
+    a fresh load at u = 0.3 come from the same distribution (two-sample KS),
+    with the fresh load's weight and, within noise, its count."""
+    a = oracle.Run(_box(1.0, ppc=600, seed=54))
+    a.set_speed_limit(0.3, 1.0)
+    b = oracle.Run(_box(0.3, ppc=600, seed=55))
+    assert stats.ks_2samp(_speeds(a, 0), _speeds(b, 0)).pvalue > 1e-3
+    assert a.weight(0) == pytest.approx(b.weight(0), rel=1e-14)
+    assert abs(a.nslots(0) - b.nslots(0)) < 6 * math.sqrt(b.nslots(0))
+
+
+@pytest.mark.parametrize("u_new", [0.5, 0.05])
+def test_lowering_keeps_f_within_noise(u_new):
+    """Lowering from u = 2 v_te: the beta-weighted totals of w and of w |v|^2
+    per species equal their values before within 5 sigma of the resampling
+    noise, sigma^2 = sum over particles of (w' beta')^2 frac(p) (1 -
+    frac(p)) (times |v|^4 for the energy), p = beta w / (beta' w')."""
+    cfg = _box(2.0, ppc=300, seed=56)
+    run = oracle.Run(cfg)
+
+    def beta(u, s2):
+        return np.minimum(1.0, u / np.sqrt(s2))
+
+    before = []
+    for s in range(2):
+        _, vx, vy, vz = run.particles(s)
+        before.append((vx * vx + vy * vy + vz * vz, run.weight(s)))
+    run.set_speed_limit(u_new, 0.5)
+    for s in range(2):
+        s2, w = before[s]
+        w1 = run.weight(s)
+        p = beta(2.0, s2) * w / (beta(u_new, s2) * w1)
+        fr = p - np.floor(p)
+        c = w1 * beta(u_new, s2)
+        _, vx, vy, vz = run.particles(s)
+        s2n = vx * vx + vy * vy + vz * vz
+        for k in (0, 1):  # moments |v|^0 and |v|^2
+            m0 = np.sum(w * beta(2.0, s2) * s2 ** k)
+            m1 = np.sum(w1 * beta(u_new, s2n) * s2n ** k)
+            sigma = math.sqrt(np.sum((c * s2 ** k) ** 2 * fr * (1 - fr)))
+            assert abs(m1 - m0) <= 5 * sigma + 1e-12 * m0, (s, k, m0, m1, sigma)
+        assert np.all(p < 255)
