@@ -129,6 +129,22 @@ typedef struct {
                            /* warm_profile                                      */
     int32_t reserved;
     double bias;           /* SLPIC_GEOM_PLATES: phi(L) in T_e/e; else unused   */
+    const double* limit_profile; /* NULL: the speed limit is u everywhere.  Else */
+                           /* a host array of nx + 1 finite positive node      */
+                           /* values of a limit v0(x) varying with position    */
+                           /* (Sec. II lets beta depend on position), linear   */
+                           /* between nodes, read by slpic_workspace_bytes and  */
+                           /* slpic_init only; u must then be finite and only  */
+                           /* sets the species weights (w = dx Z(u/vt)/ppc).   */
+                           /* A step takes the limit at x^n for the velocity   */
+                           /* map and the move (frozen over the step like      */
+                           /* E^n(x^n)); the charge and the moments take it at */
+                           /* the particle's position; the plates' wall source */
+                           /* takes it at the plate.  The cold load goes cell  */
+                           /* by cell (unit density at rest, g = f/beta at the */
+                           /* limit of the cell centre, the mean of its nodes)  */
+                           /* through the warm-load sampler; with warm_profile */
+                           /* the warm cells take that limit too.  1D only.    */
 } slpic_run_config;
 
 typedef struct {
@@ -243,21 +259,24 @@ int slpic_import_particles(void* ctx, int32_t run, int32_t species, const double
  * fractional electron-injection accumulator of one run. */
 int slpic_set_counters(void* ctx, int32_t run, int64_t step, double acc_e);
 
-/* Sync.  Raise the speed limit of one run mid-run to u (>= its current
- * limit; +INFINITY turns it into standard PIC) with time step dt from the
- * next step on (the paper lets the limit vary in time, to adjust the
+/* Sync.  Change the speed limit of one run mid-run to u (higher or lower;
+ * +INFINITY turns it into standard PIC) with time step dt from the next
+ * step on (the paper lets the limit vary in time, to adjust the
  * approximation during a simulation).  The physical distribution f = beta g
  * is kept: the species weights become those of a fresh load at u (w' = dx
  * Z(u)/ppc), and each live g-particle of the run, of velocity v, is
  * replaced by m copies, m = floor(p) + [U < p - floor(p)], p = (beta_old(|v|)
- * w) / (beta_u(|v|) w') <= w/w' (at most 255), U the first draw of its own
- * Philox stream (purpose 6, its slot, the step count); the copies keep the
- * slot order with dead slots dropped, in every run of the context (the
- * others keep each live particle once).  Then the charge and fields are
- * recomputed.  The last sort permutation is overwritten.  Copies beyond the
- * capacity are dropped with SLPIC_FLAG_CAPACITY.  SLPIC_EINVAL for u below
- * the current limit, dt <= 0, a plates run whose wall flux per step would
- * grow, or a context too large for the int32 scan of copy counts. */
+ * w) / (beta_u(|v|) w') (a raise: p <= w/w'; a lowering: p <= (beta_old /
+ * beta_u) w/w', of order |v|/<|v|> for the fast particles; at most 255), U
+ * the first draw of its own Philox stream (purpose 6, its slot, the step
+ * count); the copies keep the slot order with dead slots dropped, in every
+ * run of the context (the others keep each live particle once).  Then the
+ * charge and fields are recomputed.  The last sort permutation is
+ * overwritten.  Copies beyond the capacity are dropped with
+ * SLPIC_FLAG_CAPACITY.  SLPIC_EINVAL for u <= 0, dt <= 0, a run with a
+ * limit profile, a plates run whose wall flux per step would grow, or a
+ * resampled total of 2^31 slots or more (then nothing has changed but the
+ * last sort permutation). */
 int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* stream);
 
 /* Sync.  With tuning.retire_steady, takes every run that has retired

@@ -76,7 +76,8 @@ typedef struct {
  * two, 4..2048) and the given tuning (NULL = defaults); run->geometry must be
  * SLPIC_GEOM_SHEATH.  run->nx, dx, dt, u,
  * beta_kind, species, source_cells, seed, run_id and capacity_factor are
- * used as in slpic.h (ppc per cell of dx x dy; warm_profile must be NULL).
+ * used as in slpic.h (ppc per cell of dx x dy; warm_profile and
+ * limit_profile must be NULL: one uniform limit).
  * Returns 0 on an invalid configuration. */
 size_t slpic2d_workspace_bytes(const slpic_run_config* run, int32_t ny, const slpic2d_tuning* tuning);
 

@@ -91,14 +91,18 @@ static double profile_at(const double* p, double xi) {
     return p[k] * (1.0 - f) + p[k + 1] * f;
 }
 
-// Cells of one (run, species), appended to out; returns the particle count.
-static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, int run, int s,
+// Cells of one (run, species) loaded from the profiles prof (7 x 256),
+// appended to out; returns the particle count.  A run with a limit profile
+// samples each cell at the limit of its centre (the mean of its two nodes).
+static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, const double* prof, int run, int s,
                                  std::vector<WarmCell>& out) {
-    const double* pn = c.warm_profile + 256 * (s == 0 ? 1 : 2);
-    const double* pg = c.warm_profile + 256 * (s == 0 ? 3 : 4);
-    const double* pT = c.warm_profile + 256 * (5 + s);
+    const double* pn = prof + 256 * (s == 0 ? 1 : 2);
+    const double* pg = prof + 256 * (s == 0 ? 3 : 4);
+    const double* pT = prof + 256 * (5 + s);
+    const double* lim = c.limit_profile;
     int64_t start = 0;
     for (int cell = 0; cell < c.nx; ++cell) {
+        const double uc = lim ? 0.5 * (lim[cell] + lim[cell + 1]) : c.u;
         const double xi = ((double)cell + 0.5) / (double)c.nx;
         const double T = profile_at(pT, xi);  // not positive: the source temperature
         const double vt = T > 0.0 ? std::sqrt(T / R.mass[s]) : R.vt[s];
@@ -107,12 +111,12 @@ static int64_t plan_warm_species(const RunInfo& R, const slpic_run_config& c, in
         const double G = profile_at(pg, xi);
         double V = n > 0.0 ? G / n : 0.0;
         V = std::max(-4.0 * vt, std::min(4.0 * vt, V));
-        const double E = n * c.dx * drift_mean_inv_beta(c.beta_kind, c.u, V, vt) / R.w[s];
+        const double E = n * c.dx * drift_mean_inv_beta(c.beta_kind, uc, V, vt) / R.w[s];
         const double fl = std::floor(E);
         const U4 r = philox10((uint32_t)cell, 0u, R.run_id, ((uint32_t)kPurposeWarmCount << 24) | ((uint32_t)s << 20),
                               R.seed_lo, R.seed_hi);
         const int64_t cnt = (int64_t)fl + (u53(r.v[0], r.v[1]) < E - fl ? 1 : 0);
-        if (cnt > 0) out.push_back(WarmCell{run, s, cell, (int32_t)cnt, start, V, vt});
+        if (cnt > 0) out.push_back(WarmCell{run, s, cell, (int32_t)cnt, start, V, vt, uc});
         start += cnt;
     }
     return start;
@@ -126,7 +130,7 @@ int ceil_log2(int64_t v) {
 
 struct Layout {
     size_t runs, state, chunks, tiles, cur, x[2], vx[2], vp2[2], perm, E, E32, phi, Qacc, Qlast, hist,
-        totals, counts, push_err, Macc, btot, history, injb, active, total;
+        totals, counts, push_err, Macc, btot, history, injb, active, U, U32, total;
 };
 
 struct Plan {
@@ -141,6 +145,8 @@ struct Plan {
     int64_t total_slots = 0, total_nodes = 0, hist_entries = 0;
     int max_nodes = 0, max_src = 0, max_nkeys = 0;
     bool all_sheath = true;  // no plates or periodic run: the push without their paths
+    bool any_varlim = false; // a run with a limit profile: the push that reads the profiles
+    std::vector<double> limit_nodes;  // every run's limit at its nodes (at goff)
     Layout L{};
 };
 
@@ -178,7 +184,20 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             (plates && (c.warm_profile || c.source_cells > kPlatesMaxSource || !std::isfinite(c.bias))) ||
             (periodic && c.warm_profile))
             return SLPIC_EINVAL;
+        double umax = c.u;
+        if (c.limit_profile) {  // finite positive nodes, a finite u for the weights
+            if (!std::isfinite(c.u)) return SLPIC_EINVAL;
+            umax = 0.0;
+            for (int j = 0; j <= c.nx; ++j) {
+                const double v = c.limit_profile[j];
+                if (!(v > 0.0) || !std::isfinite(v)) return SLPIC_EINVAL;
+                umax = std::max(umax, v);
+            }
+            P.any_varlim = true;
+        }
         RunInfo& R = P.runs[r];
+        R.varlim = c.limit_profile ? 1 : 0;
+        R.umax = umax;
         R.nx = c.nx;
         R.nodes = c.nx + 1;
         R.beta_kind = c.beta_kind;
@@ -218,9 +237,17 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
             R.nload[s] = plates ? 0 : (int64_t)c.nx * sp.ppc;  // plates: the box starts empty
             // plates: the one-sided flux v_t / sqrt(2 pi) of unit density, in g-particles per step
             R.wall_flux[s] = plates ? R.vt[s] / std::sqrt(2.0 * M_PI) * c.dt / R.w[s] : 0.0;
-            if (c.warm_profile) {
+            if (c.warm_profile || (c.limit_profile && !plates)) {
+                // a limit profile loads cold cell by cell: unit density at rest,
+                // the source temperatures (rows of zeros)
+                static const std::vector<double> rest = [] {
+                    std::vector<double> p(7 * 256, 0.0);
+                    for (int k = 0; k < 256; ++k) p[256 + k] = p[512 + k] = 1.0;
+                    return p;
+                }();
                 R.warm = 1;
-                const int64_t nw = plan_warm_species(R, c, r, s, P.warm_cells);
+                const int64_t nw =
+                    plan_warm_species(R, c, c.warm_profile ? c.warm_profile : rest.data(), r, s, P.warm_cells);
                 if (nw > ((int64_t)1 << 31) - 65) return SLPIC_ECAPACITY;
                 R.cap[s] = std::max<int64_t>((int64_t)std::ceil(cf * (double)R.nload[s]), nw + 64);
                 R.nload[s] = nw;
@@ -245,6 +272,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
         R.retire = t.retire_steady ? 1 : 0;
         R.goff = goff;
         goff += R.nodes;
+        for (int j = 0; j <= c.nx; ++j) P.limit_nodes.push_back(c.limit_profile ? c.limit_profile[j] : c.u);
         P.max_nodes = std::max(P.max_nodes, R.nodes);
         P.max_src = std::max(P.max_src, c.source_cells + 1);
         P.max_nkeys = std::max(P.max_nkeys, R.nkeys);
@@ -318,6 +346,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     L.history = take(sizeof(double) * kHistoryLen * nruns);
     L.injb = take(sizeof(int4) * P.injb.size());
     L.active = take(sizeof(Chunk) * P.chunks.size());  // the push's chunks: runs not pruned
+    L.U = take(P.any_varlim ? sizeof(double) * P.total_nodes : 0);
+    L.U32 = take(P.any_varlim ? sizeof(float) * P.total_nodes : 0);
     L.total = o;
     return SLPIC_OK;
 }
@@ -374,9 +404,9 @@ void l_push(Context* c, bool push, hipStream_t s) {
     const Chunk* ch = push ? c->active : c->a.chunks;
     const int n = push ? c->n_active : (int)c->P.chunks.size();
     if (prec(c) == SLPIC_F32)
-        launch_push_f32(push, c->P.all_sheath, per, c->a, ch, n, c->P.tun.block, s);
+        launch_push_f32(push, c->P.all_sheath, c->P.any_varlim, per, c->a, ch, n, c->P.tun.block, s);
     else
-        launch_push_f64(push, c->P.all_sheath, per, c->a, ch, n, c->P.tun.block, s);
+        launch_push_f64(push, c->P.all_sheath, c->P.any_varlim, per, c->a, ch, n, c->P.tun.block, s);
 }
 void l_wall_inject(Context* c, hipStream_t s) {
     if (prec(c) == SLPIC_F32) launch_wall_inject_f32(c->a, s);
@@ -583,6 +613,8 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     a.history = (double*)(w + L.history);
     a.injb = (const int4*)(w + L.injb);
     a.ninjb = (int32_t)c->P.injb.size();
+    a.U = c->P.any_varlim ? (const double*)(w + L.U) : nullptr;
+    a.U32 = c->P.any_varlim ? (const float*)(w + L.U32) : nullptr;
     c->active = (Chunk*)(w + L.active);
     c->n_active = (int)c->P.chunks.size();
     c->btot = (long long*)(w + L.btot);
@@ -615,6 +647,14 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     if (!c->P.injb.empty())
         INIT_TRY(hipMemcpyAsync((void*)a.injb, c->P.injb.data(), sizeof(int4) * c->P.injb.size(),
                                 hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
+    std::vector<float> u32;
+    if (c->P.any_varlim) {  // the limit profiles (pageable copies: synchronised before init returns)
+        u32.assign(c->P.limit_nodes.begin(), c->P.limit_nodes.end());
+        INIT_TRY(hipMemcpyAsync((void*)a.U, c->P.limit_nodes.data(), sizeof(double) * c->P.total_nodes,
+                                hipMemcpyHostToDevice, s) ? SLPIC_EHIP : SLPIC_OK);
+        INIT_TRY(hipMemcpyAsync((void*)a.U32, u32.data(), sizeof(float) * c->P.total_nodes, hipMemcpyHostToDevice,
+                                s) ? SLPIC_EHIP : SLPIC_OK);
+    }
     launch_init_state(a, nruns, s);
     launch_zero(a.Qacc, 2 * c->P.total_nodes, s);
     launch_zero(a.Macc, 7 * c->P.total_nodes, s);
@@ -856,10 +896,11 @@ int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* str
     if (!c || run < 0 || run >= c->P.nruns || !(dt > 0.0) || !(u > 0.0)) return SLPIC_EINVAL;
     RunInfo Rn = c->P.runs[run];
     const RunInfo& R = c->P.runs[run];
-    if (!(u >= R.u)) return SLPIC_EINVAL;  // the limit may only rise (then p <= w/w')
+    if (R.varlim) return SLPIC_EINVAL;  // a run with a limit profile keeps it
     Rn.uinf = std::isinf(u) ? 1 : 0;
     Rn.u = u;
     Rn.u2 = u * u;
+    Rn.umax = u;
     Rn.dt = dt;
     Rn.dtdx = dt / R.dx;
     LimitArgs L{};
@@ -867,7 +908,6 @@ int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* str
     L.uinf = Rn.uinf;
     L.u = u;
     L.u2 = Rn.u2;
-    double most = 1.0;
     for (int s = 0; s < 2; ++s) {
         Rn.ut[s] = u / R.vt[s];
         Rn.w[s] = R.dx * mean_inv_beta(R.beta_kind, Rn.ut[s]) / (double)R.ppc[s];
@@ -884,17 +924,22 @@ int slpic_set_speed_limit(void* ctx, int32_t run, double u, double dt, void* str
             if (Rn.wall_flux[s] > R.wall_flux[s]) return SLPIC_EINVAL;
         }
         L.w[s] = Rn.w[s];
-        most = std::max(most, std::ceil(R.w[s] / Rn.w[s]));
     }
     Rn.inj_ratio = Rn.w[1] / Rn.w[0];
-    // the scan of copy counts runs in int32 over every slot
-    if ((double)c->P.total_slots * std::min(most, (double)kLimitMaxCopies) >= 2147483647.0) return SLPIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipDeviceSynchronize());
     const int nch = (int)c->P.chunks.size();
     if (prec(c) == SLPIC_F32) launch_limit_f32(c->a, L, nch, 0, s);
     else launch_limit_f64(c->a, L, nch, 0, s);
     launch_scan_ints(c->a.perm, c->P.total_slots, c->btot, s);
+    {   // the scan of copy counts runs in int32 over every slot: its exact
+        // (64-bit) total must stay below 2^31 before any copy is written
+        long long total = 0;
+        HIP_TRY(hipMemcpyAsync(&total, c->btot + scan_blocks(c->P.total_slots), sizeof total,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (total >= 2147483647LL) return SLPIC_EINVAL;
+    }
     if (prec(c) == SLPIC_F32) launch_limit_f32(c->a, L, nch, 1, s);
     else launch_limit_f64(c->a, L, nch, 1, s);
     launch_limit_finish(c->a, c->P.nruns, c->P.total_slots, c->btot, s);

@@ -65,7 +65,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     if (t.per_thread != 1 && t.per_thread != 2 && t.per_thread != 4 && t.per_thread != 8) return SLPIC_EINVAL;
     if (ny < 4 || ny > 2048 || (ny & (ny - 1))) return SLPIC_EINVAL;
     if (c->nx < 4 || c->nx > 1024 || !(c->dx > 0) || !(c->dt > 0) || !(c->u > 0) || c->nspecies != 2 ||
-        c->source_cells < 1 || c->source_cells > c->nx || c->warm_profile ||
+        c->source_cells < 1 || c->source_cells > c->nx || c->warm_profile || c->limit_profile ||
         (c->beta_kind != SLPIC_BETA_STEP && c->beta_kind != SLPIC_BETA_SMOOTH))
         return SLPIC_EINVAL;
     P.tun = t;

@@ -10,8 +10,8 @@ namespace slpic {
 #define SLPIC_DECLARE_LAUNCHERS(sfx)                                                                   \
     void launch_load_##sfx(const KArgs& a, int nchunks, int block, hipStream_t s);                     \
     void launch_load_warm_##sfx(const KArgs& a, const void* cells, int ncells, hipStream_t s);         \
-    void launch_push_##sfx(bool push, bool sheath, int per_thread, const KArgs& a, const Chunk* chunks, \
-                           int nchunks, int block, hipStream_t s);                                     \
+    void launch_push_##sfx(bool push, bool sheath, bool varlim, int per_thread, const KArgs& a,        \
+                           const Chunk* chunks, int nchunks, int block, hipStream_t s);                \
     void launch_velocity_map_##sfx(int beta_kind, double u, double dt, int64_t n, const void* vx,      \
                                    const void* c2, const void* acc, void* out, int* iters,             \
                                    hipStream_t s);                                                     \

@@ -62,7 +62,8 @@ struct RunInfo {
     int32_t ppc[kMaxSpecies];    // g-particles per cell at unit density (sets the weight)
     int32_t pruned;              // 1: retired and taken out of the push and sort work (its
                                  // particles then sit identical in both buffers)
-    int32_t pad_p;
+    int32_t varlim;              // 1: the speed limit varies with position (node values at goff)
+    double umax;                 // the largest speed limit of the run (its profile's largest node)
 };
 
 // A new (higher) speed limit for one run: the new limit and the new weights.
@@ -100,11 +101,11 @@ __host__ __device__ inline bool retired(const RunInfo& R, const RunState& st) {
 
 // One cell of a warm load: `count` particles of (run, species) at slots
 // start.., drawn from a Maxwellian of thermal speed vt drifting at V along x,
-// as f/beta.
+// as f/beta with the cell's speed limit u.
 struct WarmCell {
     int32_t run, species, cell, count;
     int64_t start;
-    double V, vt;
+    double V, vt, u;
 };
 
 // A contiguous slot range of one (run, species): one push / load / moments
@@ -152,6 +153,8 @@ struct KArgs {
     double* Macc;         // moment window accumulators [run]: 7 rows of nodes at 7*goff
     const int4* injb;     // plates: wall-injection workgroups (run, species, first particle, 0)
     int32_t ninjb;        // their count (0 without plates runs)
+    const double* U;      // speed-limit profiles: node values per run at goff (runs with varlim)
+    const float* U32;     // their float copy (float particles' velocity map and move)
 };
 
 }  // namespace slpic

@@ -41,7 +41,8 @@ class RunConfig(ctypes.Structure):
                 ("species", _Species * 2), ("seed", ctypes.c_uint64), ("run_id", ctypes.c_int32),
                 ("steady_window", ctypes.c_int32), ("capacity_factor", ctypes.c_double),
                 ("steady_tol", ctypes.c_double), ("warm_profile", ctypes.c_void_p),
-                ("geometry", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bias", ctypes.c_double)]
+                ("geometry", ctypes.c_int32), ("reserved", ctypes.c_int32), ("bias", ctypes.c_double),
+                ("limit_profile", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -190,8 +191,9 @@ def _beta_kind(v) -> int:
 
 def run_config(cfg: dict) -> RunConfig:
     """Marshal a run description (nx, dx, dt, u, beta_kind, species,
-    source_cells, seed, run, capacity_factor, geometry, bias) into the C
-    struct."""
+    source_cells, seed, run, capacity_factor, geometry, bias, limit_profile)
+    into the C struct (a limit profile's nx + 1 node values are kept alive
+    with the struct)."""
     c = RunConfig()
     c.nx = int(cfg["nx"])
     c.beta_kind = _beta_kind(cfg.get("beta_kind", "step"))
@@ -213,6 +215,13 @@ def run_config(cfg: dict) -> RunConfig:
     c.geometry = ({"sheath": GEOM_SHEATH, "plates": GEOM_PLATES, "periodic": GEOM_PERIODIC}[geom]
                   if isinstance(geom, str) else int(geom))
     c.bias = float(cfg.get("bias", 0.0))
+    prof = cfg.get("limit_profile")
+    if prof is not None:
+        a = np.ascontiguousarray(np.asarray(prof, dtype=np.float64).reshape(-1))
+        if a.size != c.nx + 1:
+            raise SlpicError("limit_profile needs nx + 1 node values")
+        c._limit = a
+        c.limit_profile = a.ctypes.data
     return c
 
 
@@ -263,7 +272,10 @@ class Sim:
         self.configs = [dict(c) for c in configs]
         self.nruns = len(self.configs)
         self.precision = precision
-        self._cfg = (RunConfig * self.nruns)(*[run_config(c) for c in self.configs])
+        structs = [run_config(c) for c in self.configs]
+        # the limit profiles the copied structs point to, alive while the library reads them
+        self._limits = [getattr(c, "_limit", None) for c in structs]
+        self._cfg = (RunConfig * self.nruns)(*structs)
         self._warm = []  # host profiles, alive while the library reads them
         if warm is not None:
             if len(warm) != self.nruns:
@@ -351,7 +363,7 @@ class Sim:
         return n.value
 
     def set_speed_limit(self, run: int, u: float, dt: float):
-        """Raise run's speed limit to u with time step dt (f = beta g kept by
+        """Change run's speed limit to u with time step dt (f = beta g kept by
         resampling the g-particles at the weight of a fresh load at u)."""
         _check(lib().slpic_set_speed_limit(self._ctx, int(run), float(u), float(dt), self._stream()),
                "slpic_set_speed_limit")

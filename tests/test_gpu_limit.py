@@ -1,10 +1,10 @@
-"""A rise of the speed limit mid-run on the HIP path (slpic_set_speed_limit)
-against the oracle: FP64 resampling bit-exact (the same copies in the same
-slots), the new weights, the recomputed fields, and lockstep steps at the
-new limit and time step; FP32 counts; a batched context where one run
-changes; and the paper's use, raising the limit to verify the result: the
-two-plate sheath run as SLPIC to 16 us and then as PIC reaches the PIC
-steady state."""
+"""A change of the speed limit mid-run on the HIP path (slpic_set_speed_limit)
+against the oracle, raised or lowered: FP64 resampling bit-exact (the same
+copies in the same slots), the new weights, the recomputed fields, and
+lockstep steps at the new limit and time step; FP32 counts; a batched
+context where one run changes; and the paper's use, raising the limit to
+verify the result: the two-plate sheath run as SLPIC to 16 us and then as
+PIC reaches the PIC steady state."""
 import math
 
 import numpy as np
@@ -25,19 +25,22 @@ def _exact(sim, run, r=0):
         assert np.array_equal(xg, xo) and np.array_equal(vxg, vxo) and np.array_equal(vpg, vpo), s
 
 
-@pytest.mark.parametrize("case", ["sheath_x3", "sheath_pic", "periodic_pic", "plates_x4"])
+@pytest.mark.parametrize("case", ["sheath_x3", "sheath_pic", "periodic_pic", "plates_x4", "sheath_lower",
+                                  "periodic_lower"])
 def test_resampling_bit_exact_f64(gpu_lib, case):
     if case.startswith("sheath"):
         cfg = workloads.small_sheath(sort_every=1, seed=61)
         warm = 30
-    elif case == "periodic_pic":
-        cfg = workloads.langmuir_box(0.3, nx=64, ppc=100, seed=62, sort_every=1)
+    elif case.startswith("periodic"):
+        cfg = workloads.langmuir_box(0.3 if case == "periodic_pic" else 1.0, nx=64, ppc=100, seed=62,
+                                     sort_every=1)
+        cfg["capacity_factor"] = 1.5  # a lowering may add copies
         warm = 10
     else:
         cfg = workloads.plates_sheath(0.0158, ppc=40, sort_every=1, seed=63)
         warm = 200
     u_new = {"sheath_x3": 3 * cfg["u"], "sheath_pic": math.inf, "periodic_pic": math.inf,
-             "plates_x4": 4 * cfg["u"]}[case]
+             "plates_x4": 4 * cfg["u"], "sheath_lower": cfg["u"] / 3, "periodic_lower": 0.2}[case]
     dt_new = cfg["dx"] / 5.0 if math.isinf(u_new) else cfg["dx"] / u_new
     if case.startswith("sheath"):
         dt_new = min(cfg["dt"], dt_new) if not math.isinf(u_new) else 0.1
@@ -103,8 +106,9 @@ def test_batched_only_one_run_changes(gpu_lib):
         assert np.array_equal(xg, live0[s][0][keep]) and np.array_equal(vxg, live0[s][1][keep])
     st = sim.status()
     assert st[0]["weight"] == pytest.approx([ra.weight(0), ra.weight(1)], rel=1e-12)
-    with pytest.raises(gpu_lib.SlpicError):
-        sim.set_speed_limit(0, 0.5 * a["u"], a["dt"])  # a rise only
+    for bad in ((0.0, a["dt"]), (0.5 * a["u"], 0.0)):
+        with pytest.raises(gpu_lib.SlpicError):
+            sim.set_speed_limit(0, *bad)
 
 
 def test_raise_to_pic_reaches_the_pic_steady_state(gpu_lib):
