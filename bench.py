@@ -157,6 +157,23 @@ def after_copy(rows):
     return rows[first:]
 
 
+# The sources of the push kernels: a counter record holds their fingerprint
+# and is reported only while it matches (a changed kernel reports null).
+PUSH_SOURCES = {
+    False: ("kernels.inc", "slpic_device.h", "slpic_internal.h", "field.inc"),
+    True: ("kernels2d.inc", "slpic_device.h", "slpic2d_internal.h"),
+}
+
+
+def push_sources_sha(two_d: bool) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in PUSH_SOURCES[two_d]:
+        with open(os.path.join(ROOT, "paper_1511_08225_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int, two_d: bool = False) -> int:
     """Per-launch HBM bytes of the push from two rocprofv3 --pmc counter files
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
@@ -185,7 +202,7 @@ def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int, two_d: bo
            "launches": len(fp),
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale,
-           "copy_fetch_kib": max(fc), "copy_write_kib": max(wc)}
+           "copy_fetch_kib": max(fc), "copy_write_kib": max(wc), "sources_sha": push_sources_sha(two_d)}
     table = json.load(open(TRAFFIC_FILE)) if os.path.exists(TRAFFIC_FILE) else {}
     table["sheath2d" if two_d else str(ppc)] = out
     with open(TRAFFIC_FILE, "w") as f:
@@ -195,19 +212,24 @@ def traffic_from(fetch_csv: str, write_csv: str, ppc: int, chunk: int, two_d: bo
 
 
 def traffic_for_2d(tile: int):
-    """Counter-measured HBM bytes per 2D push launch, if recorded for this tile."""
+    """Counter-measured HBM bytes per 2D push launch, if recorded for this
+    tile with the current kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE)).get("sheath2d")
-    return t.get("bytes_per_launch") if t and t.get("chunk") == tile else None
+    if t and t.get("chunk") == tile and t.get("sources_sha") == push_sources_sha(True):
+        return t.get("bytes_per_launch")
+    return None
 
 
 def traffic_for(ppc: int, chunk: int):
-    """Counter-measured HBM bytes per push launch, if recorded for this shape."""
+    """Counter-measured HBM bytes per push launch, if recorded for this shape
+    with the current kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE)).get(str(ppc))
-    if t and t.get("workload") == "production_sheath" and t.get("chunk") == chunk:
+    if (t and t.get("workload") == "production_sheath" and t.get("chunk") == chunk
+            and t.get("sources_sha") == push_sources_sha(False)):
         return t.get("bytes_per_launch")
     return None
 

@@ -1026,8 +1026,9 @@ static void inject(orc_run* r, int s, int64_t count) {
 
 /* The quantity the steady detector and the history watch: Phi_w = phi(0) -
  * phi(L) for the sheath; for the plates, whose end potentials are fixed, phi
- * at the mid-plane node; for the periodic box, E at node nx/4 (the peak of
- * the field of a cos(2 pi x/L) density perturbation). */
+ * at the mid-plane node; for the periodic box, the amplitude of the
+ * fundamental sin(2 pi x/L) mode of E, (2/nx) sum_j E_j sin(2 pi j/nx) (the
+ * field of a cos(2 pi x/L) density perturbation). */
 static double orc_monitor_potential(const orc_run* r) {
     if (r->cfg.geometry == ORC_GEOM_PLATES) return r->phi[r->cfg.nx / 2];
     if (r->cfg.geometry == ORC_GEOM_PERIODIC) {

@@ -440,6 +440,8 @@ int timed(Context* c, int k, hipStream_t s, F&& f) {
 int do_sort(Context* c, hipStream_t s) {
     const int nt = (int)c->P.tiles.size();
     return timed(c, 3, s, [&] {
+        // the (key, tile) counts start at zero: a tile writes only the keys it holds
+        launch_zero_ints(c->a.hist, c->P.hist_entries, s);
         if (prec(c) == SLPIC_F32) launch_sort_hist_f32(c->a, nt, 256, c->sort_lds, s);
         else launch_sort_hist_f64(c->a, nt, 256, c->sort_lds, s);
         launch_sort_scan(c->a, c->P.hist_entries, c->btot, s);

@@ -220,6 +220,8 @@ int sort2(Ctx2* c, hipStream_t s) {
     const Plan2& P = c->P;
     const int nt = P.R.stiles[0] + P.R.stiles[1];
     return timed2(c, 3, s, [&] {
+        // the (key, tile) counts start at zero: a tile writes only the keys it holds
+        launch_zero_ints(c->a.hist, P.hist_entries, s);
         if (f32(c)) launch2d_sort_hist_f32(c->a, nt, P.sort_lds, s);
         else launch2d_sort_hist_f64(c->a, nt, P.sort_lds, s);
         launch_scan_ints(c->a.hist, P.hist_entries, c->a.btot, s);

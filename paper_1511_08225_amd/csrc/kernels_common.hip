@@ -77,19 +77,42 @@ __global__ void k_scan_top(long long* btot, int nblk) {
     if (threadIdx.x == blockDim.x - 1) btot[nblk] = run;  // grand total
 }
 
-__global__ void k_scan_apply(int* h, int64_t n, const long long* btot) {
+// Launched with kScanThreads threads: each holds kScanPer consecutive
+// entries in registers (two 16-byte loads and stores where all are in range;
+// h is 16-byte aligned).
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = kScanBlock / kScanThreads;
+static_assert(kScanPer == 8, "two int4 per thread");
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int* h, int64_t n, const long long* btot) {
     __shared__ long long tmp[17];
-    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
-    const int64_t b1 = min(b0 + kScanBlock, n);
-    const int per = (kScanBlock + blockDim.x - 1) / blockDim.x;
-    const int64_t j0 = b0 + (int64_t)threadIdx.x * per, j1 = min(j0 + per, b1);
+    const int64_t j0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+    const bool full = j0 + kScanPer <= n;
+    int v[kScanPer];
+    if (full) {
+        const int4 a = *(const int4*)(h + j0), b = *(const int4*)(h + j0 + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) v[i] = j0 + i < n ? h[j0 + i] : 0;
+    }
     long long loc = 0;
-    for (int64_t j = j0; j < j1; ++j) loc += h[j];
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) loc += v[i];
     long long run = btot[blockIdx.x] + block_scan<long long>(loc, tmp, false);
-    for (int64_t j = j0; j < j1; ++j) {
-        long long c = h[j];
-        h[j] = (int)run;
-        run += c;
+    int o[kScanPer];
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        o[i] = (int)run;
+        run += v[i];
+    }
+    if (full) {
+        *(int4*)(h + j0) = make_int4(o[0], o[1], o[2], o[3]);
+        *(int4*)(h + j0 + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i)
+            if (j0 + i < n) h[j0 + i] = o[i];
     }
 }
 
@@ -131,6 +154,11 @@ __global__ void k_limit_finish(KArgs a, int nruns, int64_t total_slots, const lo
 __global__ void k_zero(double* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+__global__ void k_zero_ints(int* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // Moments: potential into row 0, accumulated sums divided by the node volume.
@@ -189,7 +217,7 @@ void launch_scan_ints(int* h, int64_t n, long long* btot, hipStream_t s) {
     const int nblk = scan_blocks(n);
     hipLaunchKernelGGL(k_scan_blocks, dim3(nblk), dim3(1024), 0, s, h, n, btot);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, btot, nblk);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(1024), 0, s, h, n, (const long long*)btot);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(kScanThreads), 0, s, h, n, (const long long*)btot);
 }
 void launch_sort_scan(const KArgs& a, int64_t hist_entries, long long* btot, hipStream_t s) {
     launch_scan_ints(a.hist, hist_entries, btot, s);
@@ -202,6 +230,12 @@ void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const l
 void launch_limit_finish(const KArgs& a, int nruns, int64_t total_slots, const long long* btot, hipStream_t s) {
     hipLaunchKernelGGL(k_limit_finish, dim3((nruns + 255) / 256), dim3(256), 0, s, a, nruns, total_slots, btot,
                        scan_blocks(total_slots));
+}
+void launch_zero_ints(int* p, int64_t n, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
 }
 void launch_zero(double* p, int64_t n, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;

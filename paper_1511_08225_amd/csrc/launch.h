@@ -37,6 +37,7 @@ void launch_scan_ints(int* h, int64_t n, long long* btot, hipStream_t s);
 void launch_sort_finish(const KArgs& a, int nruns, int64_t hist_entries, const long long* btot,
                         hipStream_t s);
 void launch_zero(double* p, int64_t n, hipStream_t s);
+void launch_zero_ints(int* p, int64_t n, hipStream_t s);
 void launch_limit_finish(const KArgs& a, int nruns, int64_t total_slots, const long long* btot, hipStream_t s);
 void launch_moments_finish(const KArgs& a, int run, double* out, hipStream_t s);
 void launch_moments_window(const KArgs& a, int run, double* out, int reset, hipStream_t s);

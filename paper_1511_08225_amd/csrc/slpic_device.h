@@ -369,8 +369,8 @@ __device__ __forceinline__ T kick1d(T vx, T c2, T a, T dt, T u, T u2, bool uinf,
 struct CellMap {
     int fb;
     float inv_fscale;
-    __device__ explicit CellMap(const RunInfo& R) : fb(R.fb), inv_fscale((float)R.inv_fscale) {}
-    __device__ CellMap(int fb_, float inv_fscale_) : fb(fb_), inv_fscale(inv_fscale_) {}
+    __device__ __forceinline__ explicit CellMap(const RunInfo& R) : fb(R.fb), inv_fscale((float)R.inv_fscale) {}
+    __device__ __forceinline__ CellMap(int fb_, float inv_fscale_) : fb(fb_), inv_fscale(inv_fscale_) {}
 };
 template <typename T> struct PosT;
 template <> struct PosT<float> {
@@ -398,6 +398,67 @@ template <> struct PosT<double> {
     }
     static __device__ __forceinline__ S dead() { return -1.0; }
 };
+
+// The lanes of the wave that hold the same sort key as this one (keys >= 0;
+// a lane with k < 0 gets 0), for the counting sorts.  The distinct keys of a
+// row are peeled one at a time, the lowest remaining lane's key each round
+// (a row of cell-sorted particles holds one or two keys); lanes left after
+// kPeelKeys rounds are grouped by the bits of their keys, one ballot per bit
+// of nbits.
+constexpr int kPeelKeys = 4;
+__device__ __forceinline__ uint64_t key_peers(int k, int nbits) {
+    uint64_t todo = __ballot(k >= 0);
+    uint64_t peers = 0;
+    for (int it = 0; it < kPeelKeys && todo; ++it) {
+        const int k0 = __builtin_amdgcn_readlane(k, __builtin_ctzll(todo));  // wave-uniform
+        const uint64_t m = __ballot(k == k0);
+        peers = (k == k0) ? m : peers;
+        todo &= ~m;
+    }
+    if (todo) {
+        const bool mine = (todo >> (threadIdx.x & 63)) & 1;
+        uint64_t p = todo;
+        for (int bit = 0; bit < nbits; ++bit) {
+            const bool on = (k >> bit) & 1;
+            const uint64_t m = __ballot(mine && on);
+            p &= on ? m : ~m;
+        }
+        peers = mine ? p : peers;
+    }
+    return peers;
+}
+
+// Runs of equal keys in a row (lane order): a lane heads a run when its key
+// differs from the previous lane's.  key_runs returns the mask of heads and
+// the previous lane's key (lane 0: its own); run_length the size of the run
+// a head lane starts.
+__device__ __forceinline__ uint64_t key_runs(int k, int lane, int& kprev) {
+    kprev = __shfl_up(k, 1);
+    return __ballot(lane == 0 || k != kprev);
+}
+__device__ __forceinline__ int run_length(uint64_t heads, int lane) {
+    const uint64_t after = heads & ~((2ull << lane) - 1);  // heads above this lane (lane 63: none)
+    return (after ? (int)__builtin_ctzll(after) : 64) - lane;
+}
+
+// Stable rank of a lane among the lanes of its row holding its key, and
+// (for the lowest such lane, rank 0) their number.  A row whose keys do not
+// decrease in lane order (a sorted row) holds each key in one run: the rank
+// is the distance to the run's head.  Other rows group lanes by key_peers.
+__device__ __forceinline__ void key_rank(int k, int nbits, int lane, int& rank, int& count) {
+    int kprev;
+    const uint64_t heads = key_runs(k, lane, kprev);
+    if (__ballot(lane > 0 && k < kprev) == 0) {  // wave-uniform: keys non-decreasing
+        const int head = 63 - (int)__builtin_clzll(heads & ((2ull << lane) - 1));
+        rank = lane - head;
+        count = rank == 0 ? run_length(heads, lane) : 0;
+    } else {
+        const uint64_t peers = key_peers(k, nbits);
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        rank = (int)__popcll(peers & lt);
+        count = (int)__popcll(peers);
+    }
+}
 
 // Orders a wave's LDS accesses: everything before is complete and visible to
 // the other lanes of the wave before anything after.
