@@ -350,9 +350,10 @@ def steady_bench(args) -> int:
     return 0
 
 
-def time_to_steady(args, runs: int = 64, plain_runs: int = 8, max_steps: int = 8192) -> dict:
-    """A bounded time-to-steady measurement for the default line: `runs`
-    sheaths of the batched sweep distribution (seed 1) from cold loads, all
+def time_to_steady(args, runs: int = 256, plain_runs: int = 16, max_steps: int = 16384) -> dict:
+    """A bounded time-to-steady measurement for the default line (about 20 s
+    on one MI355X): `runs` sheaths of the batched sweep distribution (seed 1)
+    from cold loads, all
     in one context with steady runs retired and pruned, against the first
     `plain_runs` of them one at a time (the same kernels, graph replay), each
     stopped at its device steady flag or at max_steps; a run that never flags
