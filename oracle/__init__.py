@@ -168,6 +168,8 @@ def lib():
             "orc_wave_accel": (_D, [ctypes.POINTER(_Wave), _D, _D]),
             "orc_wave_push": (None, [ctypes.POINTER(_Wave), _PD, _PD, _I64, _I64, _I32]),
             "orc2_create": (_VP, [ctypes.POINTER(_Config), _I32, _I32]),
+            "orc2_get_steady": (None, [_VP, ctypes.POINTER(_Steady)]),
+            "orc2_moments": (None, [_VP, _PD]),
             "orc2_destroy": (None, [_VP]),
             "orc2_load": (None, [_VP]),
             "orc2_step": (None, [_VP, _I32]),
@@ -628,6 +630,19 @@ class Run2D:
     def wall_potential(self) -> float:
         """Phi_w: the y-mean of phi at x = 0 (phi = 0 at the wall)."""
         return float(self.grid()["phi"][0].mean())
+
+    def steady(self) -> dict:
+        """The wall-potential steady detector of this run."""
+        d = _Steady()
+        lib().orc2_get_steady(self._h, ctypes.byref(d))
+        return d.as_dict()
+
+    def moments(self) -> np.ndarray:
+        """beta-weighted node moments, shape (7, nx + 1, ny): phi, then n,
+        Gamma_x, kinetic energy density per species."""
+        out = np.zeros(7 * (self.nx + 1) * self.ny)
+        lib().orc2_moments(self._h, _dp(out))
+        return out.reshape(7, self.nx + 1, self.ny)
 
 
 def thermal_speed(cfg: dict, s: int) -> float:

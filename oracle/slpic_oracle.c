@@ -1271,6 +1271,7 @@ void orc_get_steady(const orc_run* r, orc_steady* out) { *out = r->steady; }
 /* (x, y) plane, so v_z is a constant of the motion.                          */
 /* ======================================================================== */
 struct orc2_run {
+    orc_steady steady; /* fed with Phi_w (the y-mean of phi(0, y)) after every step */
     orc_config cfg;
     int32_t ny, tile; /* sort key: the tile x tile block of cells holding the particle */
     double w[2], qw[2], qm[2];
@@ -1296,6 +1297,8 @@ orc2_run* orc2_create(const orc_config* cfg, int32_t ny, int32_t tile) {
     orc2_run* r = (orc2_run*)calloc(1, sizeof(orc2_run));
     r->cfg = *cfg;
     r->ny = ny;
+    orc_steady_init(&r->steady, cfg->steady_window > 0 ? cfg->steady_window : (cfg->nx / 4 > 1 ? cfg->nx / 4 : 1),
+                    cfg->steady_tol > 0.0 ? cfg->steady_tol : 0.02);
     r->tile = tile > 0 ? tile : 1;
     size_t nodes = (size_t)(cfg->nx + 1) * (size_t)ny;
     for (int s = 0; s < cfg->nspecies; ++s) {
@@ -1457,6 +1460,13 @@ static void deposit2(orc2_run* r) {
     }
 }
 
+/* Phi_w of a 2D run: the y-mean of phi at x = 0 (phi = 0 at the wall). */
+static double orc2_wall_potential(const orc2_run* r) {
+    double a = 0.0;
+    for (int j = 0; j < r->ny; ++j) a += r->phi[j];
+    return a / (double)r->ny;
+}
+
 static void solve2(orc2_run* r) {
     size_t nodes = (size_t)(r->cfg.nx + 1) * r->ny;
     double* Qt = (double*)calloc(nodes, sizeof(double));
@@ -1605,7 +1615,52 @@ void orc2_step(orc2_run* r, int32_t nsteps) {
         deposit2(r);
         solve2(r);
         r->step += 1;
+        orc_steady_feed(&r->steady, orc2_wall_potential(r), r->step);
         if (cfg->sort_every > 0 && r->step % cfg->sort_every == 0) orc2_sort(r, NULL, NULL);
+    }
+}
+
+void orc2_get_steady(const orc2_run* r, orc_steady* out) { *out = r->steady; }
+
+/* beta-weighted moments at the nodes (f = beta g, Eq. 5), as in 1D: rows phi,
+ * then per species n, Gamma_x = sum w beta v_x W / dV and the kinetic energy
+ * density sum w beta (m |v|^2 / 2) W / dV, W bilinear with the y wrap, dV =
+ * dx dy (halved at the x end nodes); each row (nx + 1) ny values at i*ny + j. */
+void orc2_moments(const orc2_run* r, double* out) {
+    int ny = r->ny;
+    size_t nodes = (size_t)(r->cfg.nx + 1) * (size_t)ny;
+    int ns = r->cfg.nspecies;
+    memset(out, 0, sizeof(double) * nodes * (size_t)(1 + 3 * ns));
+    memcpy(out, r->phi, sizeof(double) * nodes);
+    for (int s = 0; s < ns; ++s) {
+        double* n = out + nodes * (size_t)(1 + 3 * s);
+        double* G = n + nodes;
+        double* K = G + nodes;
+        for (int64_t i = 0; i < r->n[s]; ++i) {
+            double xt = r->x[s][i];
+            if (xt < 0.0) continue;
+            double yt = r->y[s][i];
+            double v[3] = {r->vx[s][i], r->vy[s][i], r->vz[s][i]};
+            double v2 = norm2(v);
+            double wb = r->w[s] * beta_of_s2(r->cfg.beta_kind, r->cfg.u, v2);
+            double ke = 0.5 * r->cfg.species[s].mass * v2;
+            int cx = (int)floor(xt), cy = (int)floor(yt);
+            double fx = xt - cx, fy = yt - cy;
+            int cy1 = (cy + 1) % ny;
+            size_t idx[4] = {(size_t)cx * ny + cy, (size_t)(cx + 1) * ny + cy, (size_t)cx * ny + cy1,
+                             (size_t)(cx + 1) * ny + cy1};
+            double wt[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};
+            for (int k = 0; k < 4; ++k) {
+                n[idx[k]] += wb * wt[k];
+                G[idx[k]] += wb * wt[k] * v[0];
+                K[idx[k]] += wb * wt[k] * ke;
+            }
+        }
+        for (size_t k = 0; k < nodes; ++k) {
+            int ix = (int)(k / (size_t)ny);
+            double dV = r->cfg.dx * r->cfg.dx * ((ix == 0 || ix == r->cfg.nx) ? 0.5 : 1.0);
+            n[k] /= dV; G[k] /= dV; K[k] /= dV;
+        }
     }
 }
 

@@ -212,6 +212,12 @@ void orc2_set_particles(orc2_run* r, int32_t s, int64_t n, const double* x, cons
                         const double* vy, const double* vz);
 void orc2_set_counters(orc2_run* r, int64_t step, double acc_e);
 void orc2_get_grid(const orc2_run* r, double* Q0, double* Q1, double* phi, double* Ex, double* Ey);
+/* The steady detector of a 2D run, fed with Phi_w = mean_y phi(0, y) after
+ * every step (window max(1, nx/4) unless steady_window is set). */
+void orc2_get_steady(const orc2_run* r, orc_steady* out);
+/* beta-weighted node moments of a 2D run: 7 rows of (nx+1) ny values, phi
+ * then n, Gamma_x, kinetic energy density per species (bilinear weights). */
+void orc2_moments(const orc2_run* r, double* out);
 
 #ifdef __cplusplus
 }

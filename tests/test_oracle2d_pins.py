@@ -224,7 +224,7 @@ def test_y_uniform_2d_run_reduces_to_1d():
     # kept): the 2D charge is y-uniform, Ey vanishes and x, vx, phi follow
     # the 1D run step by step (ions are kept 4 cells from the wall, so none
     # is absorbed in 3 steps of at most one cell and nothing is injected)
-    cfg = workloads.sheath(nx=16, ppc=20, u_over_vti=3.0, seed=11, sort_every=0)
+    cfg = workloads.sheath(nx=16, ppc=20, u_over_vti=3.0, seed=11, sort_every=0, steady_window=1)
     ny = 4
     r1 = oracle.Run(cfg)
     x, vx, vy, vz = r1.particles(1)
@@ -253,6 +253,60 @@ def test_y_uniform_2d_run_reduces_to_1d():
             for j in range(ny):
                 assert np.abs(X[j * n:(j + 1) * n] - x1).max() < 1e-9
                 assert np.abs(VX[j * n:(j + 1) * n] - vx1).max() < 1e-9 * max(1e-300, np.abs(vx1).max())
+    # the y-mean of the 2D moments is the 1D moments (the 2D weight is dy
+    # times the 1D one and each 1D particle has ny copies), and both steady
+    # detectors saw the same Phi_w after every step
+    m1, m2 = r1.moments(), r2.moments().mean(axis=2)
+    for row in range(7):
+        assert np.abs(m2[row] - m1[row]).max() <= 1e-10 * max(1e-300, np.abs(m1[row]).max()), row
+    d1, d2 = r1.steady(), r2.steady()  # one-step windows: the last three Phi_w
+    assert d2["windows"] == d1["windows"] == 3
+    assert d2["window_mean"] == pytest.approx(d1["window_mean"], rel=1e-10)
+
+
+def test_moments2d_by_hand():
+    """Moments of a few particles written out with bilinear weights, the y
+    wrap and the node volumes (half at the x end nodes)."""
+    cfg = workloads.sheath(nx=6, ppc=2, u_over_vti=3.0, seed=13, sort_every=0)
+    ny = 4
+    r = oracle.Run2D(cfg, ny, load=False)
+    rng = np.random.default_rng(5)
+    parts = []
+    for s in range(2):
+        n = 7
+        X = rng.uniform(0, cfg["nx"], n)
+        Y = rng.uniform(0, ny, n)
+        Y[0] = ny - 0.3  # a particle across the y wrap
+        X[1] = 0.2       # near the symmetry plane
+        vth = oracle.thermal_speed(cfg, s)
+        VX, VY, VZ = (rng.normal(size=n) * vth * 4 for _ in range(3))
+        r.set_particles(s, X, Y, VX, VY, VZ)
+        parts.append((X, Y, VX, VY, VZ))
+    r.refresh_fields()
+    m = r.moments()
+    u = cfg["u"]
+    dx = cfg["dx"]
+    assert np.array_equal(m[0], r.grid()["phi"])
+    for s in range(2):
+        X, Y, VX, VY, VZ = parts[s]
+        w = r.weight(s)
+        mass = cfg["species"][s]["mass"]
+        want = np.zeros((3, cfg["nx"] + 1, ny))
+        for i in range(len(X)):
+            v2 = VX[i] ** 2 + VY[i] ** 2 + VZ[i] ** 2
+            b = min(1.0, u / math.sqrt(v2))
+            cx, cy = int(X[i]), int(Y[i])
+            fx, fy = X[i] - cx, Y[i] - cy
+            for (ix, iy, wt) in ((cx, cy, (1 - fx) * (1 - fy)), (cx + 1, cy, fx * (1 - fy)),
+                                 (cx, (cy + 1) % ny, (1 - fx) * fy), (cx + 1, (cy + 1) % ny, fx * fy)):
+                for row, q in enumerate((1.0, VX[i], 0.5 * mass * v2)):
+                    want[row, ix, iy] += w * b * wt * q
+        dV = np.full(cfg["nx"] + 1, dx * dx)
+        dV[0] *= 0.5
+        dV[-1] *= 0.5
+        want /= dV[None, :, None]
+        got = m[1 + 3 * s: 4 + 3 * s]
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), s
 
 
 def test_source2d_balances_ion_loss():
