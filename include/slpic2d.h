@@ -54,7 +54,10 @@ typedef struct {
     int32_t tail_groups; /* workgroups over the unsorted tail; 0 = 512           */
     int32_t sort_tile;   /* slots per sort workgroup, a multiple of 1024 up to   */
                          /* 2^20; 0 = 65536                                      */
-    int32_t reserved;
+    int32_t graph_steps; /* > 0: slpic2d_step on a non-default stream replays     */
+                         /* blocks of this many steps as one HIP graph (rounded  */
+                         /* up to a multiple of sort_every; the graph is         */
+                         /* captured on first use); 0 = direct launches          */
 } slpic2d_tuning;
 
 typedef struct {
@@ -70,6 +73,13 @@ typedef struct {
     int32_t error_flags;       /* SLPIC_FLAG_* bits (sticky)                        */
     int32_t fixed_bits;        /* F32: fraction bits of the coordinate fixed point  */
     double weight[2];          /* macroparticle weight per species, dx dy Z / ppc   */
+    int64_t steady_step;       /* step count when the wall-potential detector first */
+                               /* flagged the run steady (as slpic.h: three window  */
+                               /* means of Phi_w within steady_tol of their mean;   */
+                               /* steady_window and steady_tol of the run config,   */
+                               /* 0 = max(1, nx/4) and 0.02), -1 before             */
+    int64_t windows;           /* closed windows                                    */
+    double window_mean[3];     /* the last three window means, newest first         */
 } slpic2d_status;
 
 /* Bytes of device workspace for one 2D run with ny cells along y (a power of
@@ -89,8 +99,21 @@ int slpic2d_init(const slpic_run_config* run, int32_t ny, const slpic2d_tuning* 
                  size_t workspace_bytes, void* stream, void** out_ctx);
 
 /* Advance by nsteps steps: push and deposit, wall absorption, source
- * injection, field solve, the periodic tile sort.  Async. */
+ * injection, field solve, Phi_w into the history ring and the steady
+ * detector, the periodic tile sort.  Async (HIP-graph replays when
+ * tuning.graph_steps > 0 and stream is not the default stream). */
 int slpic2d_step(void* ctx, int32_t nsteps, void* stream);
+
+/* beta-weighted moments of f = beta g (Eq. 5) at the current state, to the
+ * caller's device buffer d_out of 7 (nx+1) ny doubles: phi, then for species
+ * 0 and 1 the density n, the flux Gamma_x = n <v_x> and the kinetic-energy
+ * density, each (nx+1) x ny row-major at i*ny + j (bilinear weights with the
+ * y wrap, node volume dx dy, halved at the x end nodes).  Async on stream. */
+int slpic2d_moments(void* ctx, double* d_out, void* stream);
+
+/* Sync.  Phi_w after each of the last min(step, 4096) steps, oldest first,
+ * to h_out (at least 4096 doubles); *n receives the count. */
+int slpic2d_wall_history(void* ctx, double* h_out, int64_t* n);
 
 /* Recompute rho from the stored particles and the fields, without pushing.
  * Async. */

@@ -31,7 +31,7 @@ constexpr int kInjectGroups2 = 16;
 
 struct Layout2 {
     size_t run, st, cur, inj, counts, x[2], y[2], vx[2], vy[2], vz2[2], perm, Q, phi, E, E32, spec, tpiv, tw,
-        hist, btot, tbeg, total;
+        hist, btot, tbeg, history, total;
 };
 
 struct Plan2 {
@@ -53,8 +53,12 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     slpic2d_tuning t{};
     if (tin) t = *tin;
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
-    if (t.sort_every < 0 || t.tile < 0 || t.margin < 0 || t.per_thread < 0 || t.tail_groups < 0 || t.sort_tile < 0)
+    if (t.sort_every < 0 || t.tile < 0 || t.margin < 0 || t.per_thread < 0 || t.tail_groups < 0 || t.sort_tile < 0 ||
+        t.graph_steps < 0)
         return SLPIC_EINVAL;
+    // a captured block of steps starts at a multiple of the sort period
+    if (t.sort_every > 0 && t.graph_steps > 0 && t.graph_steps % t.sort_every)
+        t.graph_steps = (t.graph_steps / t.sort_every + 1) * t.sort_every;
     if (t.tile == 0) t.tile = 8;
     if (t.margin == 0) t.margin = std::max(1, t.sort_every);
     if (t.per_thread == 0) t.per_thread = 1;
@@ -66,7 +70,8 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     if (ny < 4 || ny > 2048 || (ny & (ny - 1))) return SLPIC_EINVAL;
     if (c->nx < 4 || c->nx > 1024 || !(c->dx > 0) || !(c->dt > 0) || !(c->u > 0) || c->nspecies != 2 ||
         c->source_cells < 1 || c->source_cells > c->nx || c->warm_profile || c->limit_profile ||
-        (c->beta_kind != SLPIC_BETA_STEP && c->beta_kind != SLPIC_BETA_SMOOTH))
+        (c->beta_kind != SLPIC_BETA_STEP && c->beta_kind != SLPIC_BETA_SMOOTH) || c->steady_window < 0 ||
+        !(c->steady_tol >= 0.0))
         return SLPIC_EINVAL;
     P.tun = t;
     Run2D& R = P.R;
@@ -96,6 +101,8 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     R.seed_hi = (uint32_t)(c->seed >> 32);
     R.run_id = (uint32_t)c->run_id;
     R.nodes = (int64_t)(c->nx + 1) * ny;
+    R.steady_window = c->steady_window > 0 ? c->steady_window : std::max(1, c->nx / 4);
+    R.steady_tol = c->steady_tol > 0.0 ? c->steady_tol : 0.02;
     const double cf = c->capacity_factor > 1.0 ? c->capacity_factor : 1.0;
     int64_t poff = 0, hoff = 0;
     for (int s = 0; s < 2; ++s) {
@@ -160,6 +167,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     L.hist = take(sizeof(int) * P.hist_entries);
     L.btot = take(sizeof(long long) * (scan_blocks(P.hist_entries) + 1));
     L.tbeg = take(sizeof(int64_t) * 2 * (R.nkeys + 1));
+    L.history = take(sizeof(double) * kHistoryLen2);
     L.total = o;
     return SLPIC_OK;
 }
@@ -176,7 +184,9 @@ struct Ctx2 {
     int prof = 0;
     std::vector<Ev2> ev[4];
     size_t ev_used[4] = {0, 0, 0, 0};
+    hipGraphExec_t gexec = nullptr;  // graph_steps captured steps (built on first use)
     ~Ctx2() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         for (auto& v : ev)
             for (auto& e : v) {
                 if (e.a) (void)hipEventDestroy(e.a);
@@ -242,7 +252,9 @@ int refresh2(Ctx2* c, hipStream_t s) {
     return field2(c, s);
 }
 
-int one_step2(Ctx2* c, hipStream_t s) {
+// One step; `index` is the step's number modulo the capture (it decides the
+// periodic sort); the caller counts it.
+int one_step2(Ctx2* c, int64_t index, hipStream_t s) {
     int rc;
     launch2d_fill(c->a.Q, 2 * c->P.R.nodes, s);
     int prc = SLPIC_OK;
@@ -255,10 +267,32 @@ int one_step2(Ctx2* c, hipStream_t s) {
          })))
         return rc;
     if ((rc = field2(c, s))) return rc;
-    c->steps_done += 1;
+    launch2d_monitor(c->a, s);  // Phi_w into the history ring and the steady detector
     const int se = c->P.tun.sort_every;
-    if (se > 0 && c->steps_done % se == 0)
+    if (se > 0 && (index + 1) % se == 0)
         if ((rc = sort2(c, s))) return rc;
+    return SLPIC_OK;
+}
+
+// graph_steps steps captured from a step index that is a multiple of the
+// sort period (the launches read every count from the device).
+int build_graph2(Ctx2* c, hipStream_t s) {
+    hipGraph_t g = nullptr;
+    HIP2_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = SLPIC_OK;
+    for (int k = 0; k < c->P.tun.graph_steps && rc == SLPIC_OK; ++k) rc = one_step2(c, k, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != SLPIC_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return rc != SLPIC_OK ? rc : SLPIC_EHIP;
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return SLPIC_EHIP;
+    }
     return SLPIC_OK;
 }
 
@@ -324,6 +358,7 @@ int slpic2d_init(const slpic_run_config* run, int32_t ny, const slpic2d_tuning* 
     a.hist = (int*)(w + L.hist);
     a.btot = (long long*)(w + L.btot);
     a.tbeg = (int64_t*)(w + L.tbeg);
+    a.history = (double*)(w + L.history);
     // field-solve tables: twiddles exp(-2 pi i k/ny) and, per y-mode m <=
     // ny/2, the pivots of the elimination of its x-system (diagonal 2 +
     // 4 sin^2(pi m/ny) with dy = dx, off-diagonals -1, row 0 coupled to row 1
@@ -346,6 +381,7 @@ int slpic2d_init(const slpic_run_config* run, int32_t ny, const slpic2d_tuning* 
     }
     State2D st{};
     for (int sp = 0; sp < 2; ++sp) st.nslots[sp] = R.nload[sp];
+    st.steady_step = -1;
 #define INIT2_TRY(x)             \
     do {                         \
         if ((x) != hipSuccess) { \
@@ -377,10 +413,54 @@ int slpic2d_step(void* ctx, int32_t nsteps, void* stream) {
     Ctx2* c = ctx2(ctx);
     if (!c || nsteps < 0) return SLPIC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    for (int32_t k = 0; k < nsteps; ++k) {
-        int rc = one_step2(c, s);
+    const int se = c->P.tun.sort_every, gl = c->P.tun.graph_steps;
+    // graph replay on a non-default stream; profiled steps launch directly
+    const bool graphs = gl > 0 && s != nullptr && !c->prof;
+    int32_t done = 0;
+    while (done < nsteps) {
+        if (graphs && nsteps - done >= gl && (se == 0 || c->steps_done % se == 0)) {
+            if (!c->gexec) {
+                int rc = build_graph2(c, s);
+                if (rc) return rc;
+            }
+            HIP2_TRY(hipGraphLaunch(c->gexec, s));
+            c->steps_done += gl;
+            done += gl;
+            continue;
+        }
+        int rc = one_step2(c, c->steps_done, s);
         if (rc) return rc;
+        c->steps_done += 1;
+        done += 1;
     }
+    return SLPIC_OK;
+}
+
+int slpic2d_moments(void* ctx, double* d_out, void* stream) {
+    Ctx2* c = ctx2(ctx);
+    if (!c || !d_out) return SLPIC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Run2D& R = c->P.R;
+    launch2d_fill(d_out, 7 * R.nodes, s);
+    if (f32(c)) launch2d_moments_f32(c->a, std::max(R.cap[0], R.cap[1]), d_out, s);
+    else launch2d_moments_f64(c->a, std::max(R.cap[0], R.cap[1]), d_out, s);
+    launch2d_moments_finish(c->a, R.nodes, d_out, s);
+    return hipGetLastError() == hipSuccess ? SLPIC_OK : SLPIC_EHIP;
+}
+
+int slpic2d_wall_history(void* ctx, double* h_out, int64_t* n) {
+    Ctx2* c = ctx2(ctx);
+    if (!c || !h_out || !n) return SLPIC_EINVAL;
+    static_assert(kHistoryLen2 == SLPIC_HISTORY_LEN, "history length");
+    HIP2_TRY(hipDeviceSynchronize());
+    State2D st;
+    int rc = read_state(c, st);
+    if (rc) return rc;
+    std::vector<double> ring(kHistoryLen2);
+    HIP2_TRY(hipMemcpy(ring.data(), c->a.history, sizeof(double) * kHistoryLen2, hipMemcpyDeviceToHost));
+    const int64_t cnt = std::min<int64_t>(st.step, kHistoryLen2);
+    for (int64_t j = 0; j < cnt; ++j) h_out[j] = ring[(st.step - cnt + j) % kHistoryLen2];
+    *n = cnt;
     return SLPIC_OK;
 }
 
@@ -570,6 +650,9 @@ int slpic2d_status_query(void* ctx, slpic2d_status* h_out) {
     o.wall_potential = st.phi_w;
     o.error_flags = st.error;
     o.fixed_bits = c->P.tun.precision == SLPIC_F32 ? R.fb : 0;
+    o.steady_step = st.steady_step;
+    o.windows = st.nwin;
+    for (int k = 0; k < 3; ++k) o.window_mean[k] = st.win_mean[k];
     *h_out = o;
     return SLPIC_OK;
 }

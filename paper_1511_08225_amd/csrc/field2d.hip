@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "launch2d.h"
+#include "slpic_device.h"
 #include "slpic2d_internal.h"
 
 namespace slpic {
@@ -193,6 +194,30 @@ __global__ void k_finish2d(Args2D a) {
     for (int j = threadIdx.x; j < 2 * kCountSlots2; j += blockDim.x) a.counts[j] = make_int2(0, 0);
 }
 
+// After an advancing step's field solve (the step already counted by
+// k_finish2d): Phi_w into the history ring and the steady detector.
+__global__ void k_monitor2d(Args2D a) {
+    if (threadIdx.x != 0) return;
+    const Run2D& R = *a.run;
+    State2D* st = a.st;
+    const double pw = st->phi_w;
+    a.history[(st->step - 1) % kHistoryLen2] = pw;
+    steady_feed(R, st, pw);
+}
+
+// Moments: phi into row 0, the six accumulated rows divided by the node
+// volume dx dy (half at the x end nodes).
+__global__ void k_moments2d_finish(Args2D a, double* out) {
+    const Run2D& R = *a.run;
+    const int64_t nodes = R.nodes;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nodes; k += (int64_t)gridDim.x * blockDim.x) {
+        out[k] = a.phi[k];
+        const int ix = (int)(k / R.ny);
+        const double inv = 1.0 / (R.dx * R.dx * ((ix == 0 || ix == R.nx) ? 0.5 : 1.0));
+        for (int row = 1; row < 7; ++row) out[row * nodes + k] *= inv;
+    }
+}
+
 // After the sort scatter: the sorted buffer becomes current and holds exactly
 // the live particles; tile k of species s owns slots [tbeg[k], tbeg[k+1]).
 __global__ void k_sort2d_finish(Args2D a, int nblk) {
@@ -239,6 +264,15 @@ void launch2d_finish(const Args2D& a, hipStream_t s) {
 
 void launch2d_sort_finish(const Args2D& a, int nblk, hipStream_t s) {
     hipLaunchKernelGGL(k_sort2d_finish, dim3(1), dim3(256), 0, s, a, nblk);
+}
+
+void launch2d_monitor(const Args2D& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_monitor2d, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch2d_moments_finish(const Args2D& a, int64_t nodes, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments2d_finish, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 4096)), dim3(256), 0,
+                       s, a, out);
 }
 
 }  // namespace slpic

@@ -15,7 +15,8 @@ namespace slpic {
                             hipStream_t s);                                                              \
     void launch2d_inject_##sfx(const Args2D& a, int groups, hipStream_t s);                              \
     void launch2d_sort_hist_##sfx(const Args2D& a, int ntiles, size_t lds, hipStream_t s);               \
-    void launch2d_sort_scatter_##sfx(const Args2D& a, int ntiles, size_t lds, hipStream_t s);
+    void launch2d_sort_scatter_##sfx(const Args2D& a, int ntiles, size_t lds, hipStream_t s);          \
+    void launch2d_moments_##sfx(const Args2D& a, int64_t slots, double* out, hipStream_t s);
 
 SLPIC2_DECLARE_LAUNCHERS(f32)
 SLPIC2_DECLARE_LAUNCHERS(f64)
@@ -25,5 +26,7 @@ void launch2d_fill(double* p, int64_t n, hipStream_t s);
 void launch2d_field(const Args2D& a, int nx, int ny, hipStream_t s);
 void launch2d_finish(const Args2D& a, hipStream_t s);
 void launch2d_sort_finish(const Args2D& a, int nblk, hipStream_t s);
+void launch2d_monitor(const Args2D& a, hipStream_t s);
+void launch2d_moments_finish(const Args2D& a, int64_t nodes, double* out, hipStream_t s);
 
 }  // namespace slpic

@@ -9,6 +9,7 @@
 namespace slpic {
 
 constexpr int kCountSlots2 = 64;  // spread slots of the per-step particle counters
+constexpr int kHistoryLen2 = 4096;  // wall-potential ring (the 1D length)
 
 // Immutable run parameters.
 struct Run2D {
@@ -30,6 +31,9 @@ struct Run2D {
     int64_t cap[2], poff[2], nload[2];
     int64_t hoff[2];       // first sort histogram entry per species
     int64_t nodes;         // (nx + 1) * ny
+    int32_t steady_window; // steps per wall-potential window
+    int32_t pad2;
+    double steady_tol;     // relative spread of three window means that counts as steady
 };
 
 // Mutable run state, on the device.
@@ -43,8 +47,12 @@ struct alignas(64) State2D {
     double acc_e;
     double phi_w;               // y-mean of phi at x = 0 after the last solve
     int32_t error;
-    int32_t pad;
+    int32_t win_n;              // steps in the open wall-potential window
     int64_t live[2];            // live particles counted by the sort histogram
+    double win_sum;             // sum of phi_w over the open window
+    double win_mean[3];         // the last three closed window means, newest first
+    int64_t nwin;               // closed windows
+    int64_t steady_step;        // step count when first steady, -1 before
 };
 
 // Source counts of the current step (computed from the push counters).
@@ -77,6 +85,7 @@ struct Args2D {
     int64_t* tbeg;   // tile slot ranges after the last sort [2][nkeys + 1]
     int2* counts;    // [2][kCountSlots2]: (absorbed, pushed) of the last push
     Inject2D* inj;
+    double* history; // wall-potential ring [kHistoryLen2]
 };
 
 }  // namespace slpic

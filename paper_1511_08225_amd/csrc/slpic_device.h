@@ -460,6 +460,35 @@ __device__ __forceinline__ void key_rank(int k, int nbits, int lane, int& rank, 
     }
 }
 
+// Steady-state detection on the wall potential Phi_w (1D: phi(0) - phi(L);
+// 2D: the y-mean of phi(0, y); the paper calls the final state an
+// equilibrium without a formal test): steps are grouped into windows of
+// steady_window steps; when a window closes, its mean joins the last three
+// means, and the run is steady at the first step where the three means lie
+// within steady_tol * |their mean| of it (the largest deviation from their
+// average).  The step count then stays as steady_step.  Called by one thread
+// per run after each advancing solve, with st->step already counting it.
+// RI / ST: the run parameters and run state of the 1D or the 2D library.
+template <typename RI, typename ST>
+__device__ __forceinline__ void steady_feed(const RI& R, ST* st, double pw) {
+    st->win_sum += pw;
+    st->win_n += 1;
+    if (st->win_n < R.steady_window) return;
+    const double m = st->win_sum / (double)R.steady_window;
+    st->win_mean[2] = st->win_mean[1];
+    st->win_mean[1] = st->win_mean[0];
+    st->win_mean[0] = m;
+    st->nwin += 1;
+    st->win_sum = 0.0;
+    st->win_n = 0;
+    if (st->nwin >= 3 && st->steady_step < 0) {
+        const double m0 = st->win_mean[0], m1 = st->win_mean[1], m2 = st->win_mean[2];
+        const double mbar = (m0 + m1 + m2) / 3.0;
+        const double dev = fmax(fmax(fabs(m0 - mbar), fabs(m1 - mbar)), fabs(m2 - mbar));
+        if (dev <= R.steady_tol * fabs(mbar)) st->steady_step = st->step;
+    }
+}
+
 // Orders a wave's LDS accesses: everything before is complete and visible to
 // the other lanes of the wave before anything after.
 __device__ __forceinline__ void wave_sync() {

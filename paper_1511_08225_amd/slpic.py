@@ -83,7 +83,7 @@ class WaveConfig(ctypes.Structure):
 class Tuning2D(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("margin", ctypes.c_int32), ("per_thread", ctypes.c_int32), ("tail_groups", ctypes.c_int32),
-                ("sort_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sort_tile", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
 
 
 class Status2D(ctypes.Structure):
@@ -91,14 +91,16 @@ class Status2D(ctypes.Structure):
                 ("capacity", ctypes.c_int64 * 2), ("absorbed_total", ctypes.c_int64 * 2),
                 ("injected_total", ctypes.c_int64 * 2), ("pushed_total", ctypes.c_int64),
                 ("acc_e", ctypes.c_double), ("wall_potential", ctypes.c_double),
-                ("error_flags", ctypes.c_int32), ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2)]
+                ("error_flags", ctypes.c_int32), ("fixed_bits", ctypes.c_int32), ("weight", ctypes.c_double * 2),
+                ("steady_step", ctypes.c_int64), ("windows", ctypes.c_int64), ("window_mean", ctypes.c_double * 3)]
 
     def as_dict(self) -> dict:
         return {"step": self.step, "nslots": list(self.nslots), "nsorted": list(self.nsorted),
                 "capacity": list(self.capacity), "absorbed_total": list(self.absorbed_total),
                 "injected_total": list(self.injected_total), "pushed_total": self.pushed_total,
                 "acc_e": self.acc_e, "wall_potential": self.wall_potential, "error_flags": self.error_flags,
-                "fixed_bits": self.fixed_bits, "weight": list(self.weight)}
+                "fixed_bits": self.fixed_bits, "weight": list(self.weight), "steady_step": self.steady_step,
+                "windows": self.windows, "window_mean": list(self.window_mean)}
 
 
 _lib = None
@@ -167,6 +169,8 @@ def lib():
             "slpic2d_status_query": (ctypes.c_int, [_P, ctypes.POINTER(Status2D)]),
             "slpic2d_profile": (ctypes.c_int, [_P, i32]),
             "slpic2d_profile_read": (ctypes.c_int, [_P, _PD, _PI64]),
+            "slpic2d_moments": (ctypes.c_int, [_P, _P, _P]),
+            "slpic2d_wall_history": (ctypes.c_int, [_P, _PD, _PI64]),
             "slpic2d_destroy": (None, [_P]),
             "slpic_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         }
@@ -542,7 +546,7 @@ class Sim2D:
     """One 2D3V sheath (y periodic over ny cells, dy = dx) on one GPU."""
 
     def __init__(self, config: dict, ny: int, precision="f32", sort_every=8, tile=8, margin=0, per_thread=0,
-                 tail_groups=0, sort_tile=0, device="cuda"):
+                 tail_groups=0, sort_tile=0, graph_steps=0, device="cuda"):
         self.config = dict(config)
         self.nx, self.ny = int(config["nx"]), int(ny)
         self.precision = precision
@@ -551,6 +555,7 @@ class Sim2D:
         t.precision = {"f32": SLPIC_F32, "f64": SLPIC_F64}[precision]
         t.sort_every, t.tile, t.margin = int(sort_every), int(tile), int(margin)
         t.per_thread, t.tail_groups, t.sort_tile = int(per_thread), int(tail_groups), int(sort_tile)
+        t.graph_steps = int(graph_steps)
         self._tun = t
         L = lib()
         nbytes = L.slpic2d_workspace_bytes(ctypes.byref(self._cfg), self.ny, ctypes.byref(t))
@@ -631,6 +636,20 @@ class Sim2D:
         _check(lib().slpic2d_export_perm(self._ctx, species, p.ctypes.data_as(_PI32), ctypes.byref(n)),
                "slpic2d_export_perm")
         return p[: n.value]
+
+    def moments(self) -> torch.Tensor:
+        """beta-weighted node moments (7, nx + 1, ny) on the device: phi, then
+        n, Gamma_x, kinetic energy density per species."""
+        out = torch.empty(7 * (self.nx + 1) * self.ny, dtype=torch.float64, device=self.device)
+        _check(lib().slpic2d_moments(self._ctx, _P(out.data_ptr()), self._stream()), "slpic2d_moments")
+        return out.view(7, self.nx + 1, self.ny)
+
+    def wall_history(self) -> np.ndarray:
+        """Phi_w after each of the last min(step, 4096) steps, oldest first."""
+        out = np.zeros(4096)
+        n = ctypes.c_int64(0)
+        _check(lib().slpic2d_wall_history(self._ctx, _dp(out), ctypes.byref(n)), "slpic2d_wall_history")
+        return out[:n.value].copy()
 
     def profile(self, enable: int):
         _check(lib().slpic2d_profile(self._ctx, int(enable)), "slpic2d_profile")
