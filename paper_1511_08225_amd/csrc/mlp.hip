@@ -1,8 +1,8 @@
 // mlp.hip -- the warm-start network on gfx950: 4 -> 256 -> 256 -> 256 -> 1792,
 // ReLU after the hidden layers.  Weights, biases, inputs and stored
 // activations are BF16 (round to nearest even from FP32); products
-// accumulate in FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16), one
-// wavefront per 16x16 output tile.  Training: backward on the same BF16
+// accumulate in FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16, operand
+// blocks staged in LDS), four wavefronts per 32x32 output block.  Training: backward on the same BF16
 // operands (output and hidden gradients rounded to BF16 before each
 // product), FP32 weight gradients, Adam on an FP32 master copy.
 //
@@ -27,7 +27,6 @@ constexpr int64_t oW4 = ob3 + kHid, ob4 = oW4 + (int64_t)kOut * kHid;
 static_assert(ob4 + kOut == SLPIC_MLP_PARAMS, "parameter layout");
 
 using bf16 = uint16_t;
-typedef short v4i16 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (finite values)
@@ -41,43 +40,80 @@ __device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((uin
 enum Epi { kHidden = 0, kOutput = 1, kMasked = 2, kGrad = 3 };
 
 // C[m][n] = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
-// B(k, n) = B[k sbk + n sbn] (BF16), M, N, K multiples of 16; wavefront w of
-// the grid computes output tile w (row-major over the N/16 tile columns).
-// Lane l holds A rows i = l % 16 and B columns i, k = 4 (l / 16) + 0..3 of
-// each 16-deep slice; the accumulator holds rows 4 (l / 16) + 0..3 of
-// column l % 16.  Epilogues:
+// B(k, n) = B[k sbk + n sbn] (BF16), M, N, K multiples of 16.  A workgroup of
+// four wavefronts computes a 32 x 32 block of C, wavefront w the 16 x 16 tile
+// at rows 16 (w / 2), columns 16 (w % 2), on gfx950's v_mfma_f32_16x16x32_bf16
+// (lane l holds A row l % 16 and B column l % 16 at k = 8 (l / 16) + 0..7;
+// the accumulator holds rows 4 (l / 16) + 0..3 of column l % 16).  Each step
+// of 64 k stages the A block [32 m][64 k] and the B block [32 n][64 k] in LDS,
+// k contiguous in both, filled by one 16-byte global load per thread along
+// whichever index is contiguous in memory (k, or m / n, then written to LDS
+// element by element); rows past M or N and k past K are zero.  Epilogues:
 //   kHidden: out_bf16[m][n] = bf16(max(acc + bias[n], 0))     (ldo)
 //   kOutput: out_f32[m][n]  = acc + bias[n]
 //   kMasked: out_bf16[m][n] = bf16(acc * (h[m][n] > 0))        (h: ldo)
 //   kGrad:   out_f32[m][n]  = acc
+constexpr int kBlk = 32;            // block tile side (m and n)
+constexpr int kKs = 64;             // k per staged step
+constexpr int kLdsRow = kKs + 8;    // padded LDS row (bf16): 144 B, rows start 16 B apart mod 128
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
+
+// One operand block [32 rows][64 k] into LDS rows (k contiguous): rows r of
+// the operand are X[(r0 + r) srow + (k0 + k) sk]; 256 threads, 8 elements each.
+__device__ __forceinline__ void stage_block(const bf16* __restrict__ X, int64_t srow, int64_t sk, int r0,
+                                            int rows, int k0, int K, bf16 (*L)[kLdsRow]) {
+    const int t = threadIdx.x;
+    if (sk == 1) {  // 8 consecutive k of one row
+        const int r = t >> 3, k = (t & 7) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + r < rows && k0 + k < K) v = *(const uint4*)(X + (int64_t)(r0 + r) * srow + (k0 + k));
+        *(uint4*)&L[r][k] = v;
+    } else if (srow == 1) {  // 8 consecutive rows at one k
+        const int k = t >> 2, r = (t & 3) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + r < rows && k0 + k < K) v = *(const uint4*)(X + (int64_t)(r0 + r) + (int64_t)(k0 + k) * sk);
+        const bf16* e = (const bf16*)&v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) L[r + j][k] = e[j];
+    } else {  // neither index contiguous: element by element
+        for (int q = t; q < kBlk * kKs; q += blockDim.x) {
+            const int r = q / kKs, k = q % kKs;
+            L[r][k] = (r0 + r < rows && k0 + k < K) ? X[(int64_t)(r0 + r) * srow + (int64_t)(k0 + k) * sk] : (bf16)0;
+        }
+    }
+}
+
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int64_t sam, int64_t sak,
                                               const bf16* __restrict__ B, int64_t sbk, int64_t sbn, int M, int N,
                                               int K, const bf16* __restrict__ bias, const bf16* __restrict__ h,
                                               void* __restrict__ out, int64_t ldo) {
-    const int lane = threadIdx.x & 63;
-    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int tn_count = N / 16;
-    if (tile >= (int64_t)(M / 16) * tn_count) return;  // wave-uniform
-    const int tm = (int)(tile / tn_count), tn = (int)(tile % tn_count);
+    __shared__ __align__(16) bf16 As[kBlk][kLdsRow];
+    __shared__ __align__(16) bf16 Bs[kBlk][kLdsRow];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int bn_count = (N + kBlk - 1) / kBlk;
+    const int bm = (int)(blockIdx.x / bn_count) * kBlk, bn = (int)(blockIdx.x % bn_count) * kBlk;
     const int i = lane & 15, kq = lane >> 4;
-    const bf16* a_row = A + (int64_t)(tm * 16 + i) * sam;
-    const bf16* b_col = B + (int64_t)(tn * 16 + i) * sbn;
+    const int ar = 16 * (w >> 1) + i, bc = 16 * (w & 1) + i;  // this lane's A row and B column in the block
     v4f32 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const int kb = k0 + 4 * kq;
-        v4i16 a, b;
+    for (int k0 = 0; k0 < K; k0 += kKs) {
+        stage_block(A, sam, sak, bm, M, k0, K, As);  // A(m, k): rows m
+        stage_block(B, sbn, sbk, bn, N, k0, K, Bs);  // B(k, n): rows n
+        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            a[j] = (short)a_row[(int64_t)(kb + j) * sak];
-            b[j] = (short)b_col[(int64_t)(kb + j) * sbk];
+        for (int kk = 0; kk < kKs; kk += 32) {
+            const v8bf16 a = *(const v8bf16*)&As[ar][kk + 8 * kq];
+            const v8bf16 b = *(const v8bf16*)&Bs[bc][kk + 8 * kq];
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        __syncthreads();
     }
-    const int col = tn * 16 + i;
+    const int col = bn + 16 * (w & 1) + i;
+    if (col >= N) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int row = tm * 16 + 4 * kq + r;
+        const int row = bm + 16 * (w >> 1) + 4 * kq + r;
+        if (row >= M) continue;
         const int64_t o = (int64_t)row * ldo + col;
         if (EPI == kHidden) {
             ((bf16*)out)[o] = to_bf16(fmaxf(acc[r] + from_bf16(bias[col]), 0.f));
@@ -94,9 +130,9 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16* __restrict__ A, int64_
 template <int EPI>
 void gemm(const bf16* A, int64_t sam, int64_t sak, const bf16* B, int64_t sbk, int64_t sbn, int M, int N, int K,
           const bf16* bias, const bf16* h, void* out, int64_t ldo, hipStream_t s) {
-    const int64_t tiles = (int64_t)(M / 16) * (N / 16);
-    hipLaunchKernelGGL(k_gemm<EPI>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, A, sam, sak, B, sbk, sbn,
-                       M, N, K, bias, h, out, ldo);
+    const int64_t blocks = (int64_t)((M + kBlk - 1) / kBlk) * ((N + kBlk - 1) / kBlk);
+    hipLaunchKernelGGL(k_gemm<EPI>, dim3((unsigned)blocks), dim3(256), 0, s, A, sam, sak, B, sbk, sbn, M, N, K, bias,
+                       h, out, ldo);
 }
 
 // First layer (K = 4): x -> bf16(x), h1 = bf16(max(x W1^T + b1, 0)).
