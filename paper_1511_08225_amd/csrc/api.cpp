@@ -620,7 +620,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     c->active = (Chunk*)(w + L.active);
     c->n_active = (int)c->P.chunks.size();
     c->btot = (long long*)(w + L.btot);
-    c->field_lds = (size_t)c->P.max_nodes * 8 + 32 * 8;
+    c->field_lds = (size_t)(c->P.max_nodes + kFieldTmp) * 8;
     c->sort_lds = (size_t)4 * c->P.max_nkeys * sizeof(int);
     c->source_field_lds = c->field_lds + (size_t)2 * c->P.max_src * 8;
 

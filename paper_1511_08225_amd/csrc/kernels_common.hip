@@ -42,7 +42,10 @@ __global__ void k_init_state(KArgs a, int nruns) {
 __global__ __launch_bounds__(kFieldThreads) void k_field(KArgs a, int advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* D = (double*)smem;
-    field_solve(a, blockIdx.x, a.state + blockIdx.x, advance, D, D + a.runs[blockIdx.x].nodes);
+    const RunInfo& R = a.runs[blockIdx.x];
+    ChargeRegs qc;
+    load_charge(a, R, qc);
+    field_solve(a, R, blockIdx.x, a.state + blockIdx.x, advance, D, D + R.nodes, qc);
 }
 
 // Exclusive scan of the sort histogram, in place, over all (run, species)

@@ -22,6 +22,8 @@ constexpr int kGeomPeriodic = 2;      // periodic box, no walls, no source
 // 64 KiB of LDS (3 * 8 * 2730 bytes)
 constexpr int kMaxCells = 2729;
 constexpr int kFieldThreads = 1024;   // field solve: threads of the per-run workgroup
+constexpr int kFieldTmp = 32;         // field solve: LDS doubles after the node row (two scans' wave totals)
+static_assert(2 * (kFieldThreads / 64) <= kFieldTmp, "each scan of the solve keeps its own wave totals");
 // field solve: nodes per thread kept in registers (every run's cells fit the
 // 1024-thread workgroup; a longer unrolled row would only cost registers)
 constexpr int kFieldPer = (kMaxCells + kFieldThreads - 1) / kFieldThreads;
