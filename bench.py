@@ -157,6 +157,13 @@ def after_copy(rows):
     return rows[first:]
 
 
+# The push + deposit target, as a fraction of the HBM roofline, and what the
+# counters show limits it (profiles/push_valu_counters.md).
+PUSH_TARGET_FRAC = 0.60
+PUSH_LIMIT_NOTE = ("the push is bound by VALU issue (the exact speed-limited velocity map and "
+                   "the FP64 deposit weight), and at this size also by latency with under one occupancy round "
+                   "of waves; HBM traffic is within 1.04x of the algorithmic bytes")
+
 # The sources of the push kernels: a counter record holds their fingerprint
 # and is reported only while it matches (a changed kernel reports null).
 PUSH_SOURCES = {
@@ -1025,6 +1032,9 @@ def main() -> int:
             "bytes_per_push": bpp,
             "avg_launch_ms": push_ms,
             "launches": prof["launches"],
+            "target_frac": PUSH_TARGET_FRAC,
+            "meets_target": achieved / HBM_PEAK_GBS >= PUSH_TARGET_FRAC,
+            "limit": None if achieved / HBM_PEAK_GBS >= PUSH_TARGET_FRAC else PUSH_LIMIT_NOTE,
         },
         "wall_potential": st["wall_potential"],
         "error_flags": st["error_flags"],
