@@ -375,7 +375,7 @@ def time_to_steady(args, runs: int = 256, plain_runs: int = 16, max_steps: int =
     `runs` sheaths are loaded warm from its prediction and batched the same
     way; the line gives their time to the flag, the preparation time apart,
     and how many settle within 2 % of the cold run's window mean (the
-    judge)."""
+    reference)."""
     import torch
     import workloads
     from paper_1511_08225_amd import autotune, slpic
@@ -430,7 +430,7 @@ def time_to_steady(args, runs: int = 256, plain_runs: int = 16, max_steps: int =
         warm_out["speedup_vs_plain"] = (plain_mean * len(cfgs)) / w if w > 0 else None
         warm_out["note"] = ("the warm runs' flag is their own detector's; a warm load settles in a different "
                             "quasi-steady state than the cold run (within_2pct_of_cold counts the runs that "
-                            "agree with the cold judge), so this ratio is not the warm start's gain")
+                            "agree with the cold reference), so this ratio is not the warm start's gain")
     return {
         "metric": "time to the steady sheath, batched (cold start) vs plain one at a time", "unit": "s",
         "runs": len(cfgs), "plain_runs_timed": len(plain), "max_steps": max_steps, "launch": params,
@@ -473,7 +473,7 @@ def warm_bench(args) -> int:
     over --horizon steps, the network trained on them in the library's
     kernels, then --eval-runs held-out runs (seed 3).  Reports (1) the
     prediction of the late wall potential against the held-out cold runs
-    (the judge: their mean over the last quarter of the horizon) beside the
+    (the reference: their mean over the last quarter of the horizon) beside the
     naive prediction (the training mean) and beside the cold runs' own
     running estimate, with the cold steps each prediction is worth; (2) the
     held-out runs loaded warm from the prediction, and from their own late
@@ -534,7 +534,7 @@ def warm_bench(args) -> int:
     worth_net = [steps_worth(r, e_net[r]) for r in range(n)]
     worth_naive = [steps_worth(r, e_naive[r]) for r in range(n)]
     prediction = {
-        "judge": "held-out cold run: mean Phi_w over the last quarter of the horizon",
+        "reference": "held-out cold run: mean Phi_w over the last quarter of the horizon",
         "median_rel_err_network": float(np.median(e_net)), "median_rel_err_naive_mean": float(np.median(e_naive)),
         "network_better_than_naive": int((e_net < e_naive).sum()),
         "median_rel_err_cold_estimate": {f"H/{d}": float(np.median(cold_estimate_err(H // d))) for d in (8, 4, 2)},

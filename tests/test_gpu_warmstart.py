@@ -50,7 +50,7 @@ def test_warm_start_network_gains_over_cold_runs(gpu_lib):
     """What the trained network gains over the method without it, on
     held-out sheaths: its prediction of the late wall potential (the cold
     run's mean over the last quarter of 2048 steps, plain cold-start SLPIC
-    being the judge) is available before the first step, and it is closer to
+    being the reference) is available before the first step, and it is closer to
     that reference than the naive prediction (the training runs' mean) and
     than the cold run's own running estimate (its latest nx/4-step window)
     after a quarter of the run.  192 training sheaths, 32 held out, cells
