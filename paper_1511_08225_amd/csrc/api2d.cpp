@@ -22,7 +22,7 @@ namespace {
 
 constexpr size_t kAlign2 = 256;
 size_t up2(size_t n) { return (n + kAlign2 - 1) / kAlign2 * kAlign2; }
-constexpr int kInjectGroups2 = 16;
+constexpr int kInjectGroups2 = 256;  // source injection: a step's new particles (FP64 draws each) spread over the chip
 
 #define HIP2_TRY(x)                                    \
     do {                                               \
