@@ -241,8 +241,8 @@ int sort2(Ctx2* c, hipStream_t s) {
     });
 }
 
-int field2(Ctx2* c, hipStream_t s) {
-    return timed2(c, 2, s, [&] { launch2d_field(c->a, c->P.R.nx, c->P.R.ny, s); });
+int field2(Ctx2* c, hipStream_t s, int advance = 0) {
+    return timed2(c, 2, s, [&] { launch2d_field(c->a, c->P.R.nx, c->P.R.ny, advance, s); });
 }
 
 int refresh2(Ctx2* c, hipStream_t s) {
@@ -266,8 +266,7 @@ int one_step2(Ctx2* c, int64_t index, hipStream_t s) {
              launch2d_finish(c->a, s);
          })))
         return rc;
-    if ((rc = field2(c, s))) return rc;
-    launch2d_monitor(c->a, s);  // Phi_w into the history ring and the steady detector
+    if ((rc = field2(c, s, 1))) return rc;  // with Phi_w into the history ring and the steady detector
     const int se = c->P.tun.sort_every;
     if (se > 0 && (index + 1) % se == 0)
         if ((rc = sort2(c, s))) return rc;

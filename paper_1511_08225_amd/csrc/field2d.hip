@@ -121,8 +121,9 @@ __global__ void k_tri2d(Args2D a) {
 }
 
 // Row i < nx: phi from its y-modes; row 0 also gives Phi_w = mean_y phi(0, y)
-// (phi = 0 at the wall).
-__global__ void k_fft_inv2d(Args2D a, int lg) {
+// (phi = 0 at the wall) and, after an advancing step (already counted by
+// k_finish2d), puts it into the history ring and the steady detector.
+__global__ void k_fft_inv2d(Args2D a, int lg, int advance) {
     const Run2D& R = *a.run;
     const int ny = R.ny, i = blockIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -148,7 +149,15 @@ __global__ void k_fft_inv2d(Args2D a, int lg) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.st->phi_w = red[0] * inv;
+    if (threadIdx.x == 0) {
+        State2D* st = a.st;
+        const double pw = red[0] * inv;
+        st->phi_w = pw;
+        if (advance) {
+            a.history[(st->step - 1) % kHistoryLen2] = pw;
+            steady_feed(R, st, pw);
+        }
+    }
 }
 
 // E = -grad phi at every node: centred differences (periodic in y; in x:
@@ -194,17 +203,6 @@ __global__ void k_finish2d(Args2D a) {
     for (int j = threadIdx.x; j < 2 * kCountSlots2; j += blockDim.x) a.counts[j] = make_int2(0, 0);
 }
 
-// After an advancing step's field solve (the step already counted by
-// k_finish2d): Phi_w into the history ring and the steady detector.
-__global__ void k_monitor2d(Args2D a) {
-    if (threadIdx.x != 0) return;
-    const Run2D& R = *a.run;
-    State2D* st = a.st;
-    const double pw = st->phi_w;
-    a.history[(st->step - 1) % kHistoryLen2] = pw;
-    steady_feed(R, st, pw);
-}
-
 // Moments: phi into row 0, the six accumulated rows divided by the node
 // volume dx dy (half at the x end nodes).
 __global__ void k_moments2d_finish(Args2D a, double* out) {
@@ -246,14 +244,14 @@ void launch2d_fill(double* p, int64_t n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill2d, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, n);
 }
 
-void launch2d_field(const Args2D& a, int nx, int ny, hipStream_t s) {
+void launch2d_field(const Args2D& a, int nx, int ny, int advance, hipStream_t s) {
     int lg = 0;
     while ((1 << lg) < ny) ++lg;
     const size_t lds = sizeof(double2) * (size_t)ny;
     hipLaunchKernelGGL(k_fft_fwd2d, dim3(nx), dim3(ny / 2), lds, s, a, lg);
     const int rows = (nx + 63) / 64 * 64;
     hipLaunchKernelGGL(k_tri2d, dim3(ny / 2 + 1), dim3(rows), (size_t)nx * 24, s, a);
-    hipLaunchKernelGGL(k_fft_inv2d, dim3(nx), dim3(ny / 2), lds, s, a, lg);
+    hipLaunchKernelGGL(k_fft_inv2d, dim3(nx), dim3(ny / 2), lds, s, a, lg, advance);
     const int64_t nodes = (int64_t)(nx + 1) * ny;
     hipLaunchKernelGGL(k_efield2d, dim3((unsigned)std::min<int64_t>((nodes + 255) / 256, 8192)), dim3(256), 0, s, a);
 }
@@ -264,10 +262,6 @@ void launch2d_finish(const Args2D& a, hipStream_t s) {
 
 void launch2d_sort_finish(const Args2D& a, int nblk, hipStream_t s) {
     hipLaunchKernelGGL(k_sort2d_finish, dim3(1), dim3(256), 0, s, a, nblk);
-}
-
-void launch2d_monitor(const Args2D& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_monitor2d, dim3(1), dim3(64), 0, s, a);
 }
 
 void launch2d_moments_finish(const Args2D& a, int64_t nodes, double* out, hipStream_t s) {

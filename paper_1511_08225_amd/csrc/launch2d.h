@@ -23,10 +23,11 @@ SLPIC2_DECLARE_LAUNCHERS(f64)
 #undef SLPIC2_DECLARE_LAUNCHERS
 
 void launch2d_fill(double* p, int64_t n, hipStream_t s);
-void launch2d_field(const Args2D& a, int nx, int ny, hipStream_t s);
+// advance: the solve ends an advancing step (Phi_w into the history ring
+// and the steady detector)
+void launch2d_field(const Args2D& a, int nx, int ny, int advance, hipStream_t s);
 void launch2d_finish(const Args2D& a, hipStream_t s);
 void launch2d_sort_finish(const Args2D& a, int nblk, hipStream_t s);
-void launch2d_monitor(const Args2D& a, hipStream_t s);
 void launch2d_moments_finish(const Args2D& a, int64_t nodes, double* out, hipStream_t s);
 
 }  // namespace slpic
