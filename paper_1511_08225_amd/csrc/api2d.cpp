@@ -63,7 +63,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     if (t.margin == 0) t.margin = std::max(1, t.sort_every);
     if (t.per_thread == 0) t.per_thread = 1;
     if (t.tail_groups == 0) t.tail_groups = 512;
-    if (t.sort_tile == 0) t.sort_tile = 65536;
+    if (t.sort_tile == 0) t.sort_tile = 32768;  // 512 x 512 sheath: 0.392 ms per step (65536: 0.402)
     if (t.sort_tile < 1024 || t.sort_tile > (1 << 20) || (t.sort_tile & 1023)) return SLPIC_EINVAL;
     if (t.tile > 64 || t.margin > 32 || t.tail_groups > 65536) return SLPIC_EINVAL;
     if (t.per_thread != 1 && t.per_thread != 2 && t.per_thread != 4 && t.per_thread != 8) return SLPIC_EINVAL;
