@@ -53,7 +53,7 @@ typedef struct {
     int32_t per_thread;  /* particles per push thread and pass: 1, 2, 4, 8; 0 = 1 */
     int32_t tail_groups; /* workgroups over the unsorted tail; 0 = 512           */
     int32_t sort_tile;   /* slots per sort workgroup, a multiple of 1024 up to   */
-                         /* 2^20; 0 = 32768                                      */
+                         /* 32768; 0 = 32768                                     */
     int32_t graph_steps; /* > 0: slpic2d_step on a non-default stream replays     */
                          /* blocks of this many steps as one HIP graph (rounded  */
                          /* up to a multiple of sort_every; the graph is         */

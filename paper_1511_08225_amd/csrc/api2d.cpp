@@ -38,7 +38,7 @@ struct Plan2 {
     slpic2d_tuning tun{};
     Run2D R{};
     int64_t total_slots = 0, hist_entries = 0;
-    size_t push_lds = 0, sort_lds = 0;
+    size_t push_lds = 0, sort_lds = 0, scatter_lds = 0;
     Layout2 L{};
 };
 
@@ -64,7 +64,8 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     if (t.per_thread == 0) t.per_thread = 1;
     if (t.tail_groups == 0) t.tail_groups = 512;
     if (t.sort_tile == 0) t.sort_tile = 32768;  // 512 x 512 sheath: 0.392 ms per step (65536: 0.402)
-    if (t.sort_tile < 1024 || t.sort_tile > (1 << 20) || (t.sort_tile & 1023)) return SLPIC_EINVAL;
+    // the scatter keeps per-wave offsets within a tile's run of one key in 16 bits
+    if (t.sort_tile < 1024 || t.sort_tile > 32768 || (t.sort_tile & 1023)) return SLPIC_EINVAL;
     if (t.tile > 64 || t.margin > 32 || t.tail_groups > 65536) return SLPIC_EINVAL;
     if (t.per_thread != 1 && t.per_thread != 2 && t.per_thread != 4 && t.per_thread != 8) return SLPIC_EINVAL;
     if (ny < 4 || ny > 2048 || (ny & (ny - 1))) return SLPIC_EINVAL;
@@ -135,8 +136,10 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     P.hist_entries = hoff;
     const size_t tsz = t.precision == SLPIC_F32 ? 4 : 8;
     P.push_lds = (size_t)R.win * R.win * (2 * tsz + 8);
-    P.sort_lds = (size_t)4 * R.nkeys * sizeof(int);
-    if (P.push_lds > 65536 || P.sort_lds > 65536) return SLPIC_EINVAL;
+    P.sort_lds = (size_t)R.nkeys * sizeof(int);  // the tile's key counts
+    // the tile's first destination per key, then four waves' packed offsets
+    P.scatter_lds = (size_t)R.nkeys * sizeof(int) + (size_t)4 * ((R.nkeys + 1) / 2) * sizeof(uint32_t);
+    if (P.push_lds > 65536 || P.sort_lds > 65536 || P.scatter_lds > 65536) return SLPIC_EINVAL;
     Layout2& L = P.L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -235,8 +238,8 @@ int sort2(Ctx2* c, hipStream_t s) {
         if (f32(c)) launch2d_sort_hist_f32(c->a, nt, P.sort_lds, s);
         else launch2d_sort_hist_f64(c->a, nt, P.sort_lds, s);
         launch_scan_ints(c->a.hist, P.hist_entries, c->a.btot, s);
-        if (f32(c)) launch2d_sort_scatter_f32(c->a, nt, P.sort_lds, s);
-        else launch2d_sort_scatter_f64(c->a, nt, P.sort_lds, s);
+        if (f32(c)) launch2d_sort_scatter_f32(c->a, nt, P.scatter_lds, s);
+        else launch2d_sort_scatter_f64(c->a, nt, P.scatter_lds, s);
         launch2d_sort_finish(c->a, scan_blocks(P.hist_entries), s);
     });
 }
