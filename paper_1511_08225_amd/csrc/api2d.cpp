@@ -137,8 +137,8 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     const size_t tsz = t.precision == SLPIC_F32 ? 4 : 8;
     P.push_lds = (size_t)R.win * R.win * (2 * tsz + 8);
     P.sort_lds = (size_t)R.nkeys * sizeof(int);  // the tile's key counts
-    // the tile's first destination per key, then four waves' packed offsets
-    P.scatter_lds = (size_t)R.nkeys * sizeof(int) + (size_t)4 * ((R.nkeys + 1) / 2) * sizeof(uint32_t);
+    // four waves' packed per-key offsets
+    P.scatter_lds = (size_t)4 * ((R.nkeys + 1) / 2) * sizeof(uint32_t);
     if (P.push_lds > 65536 || P.sort_lds > 65536 || P.scatter_lds > 65536) return SLPIC_EINVAL;
     Layout2& L = P.L;
     size_t o = 0;
