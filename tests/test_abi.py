@@ -109,6 +109,12 @@ def test_2d_workspace_planning_validates_configs():
         tb = slpic.Tuning2D()
         setattr(tb, field, val)
         assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(tb)) == 0, field
+    # sort tiles: multiples of 1024 up to 32768 slots (the scatter's per-wave
+    # offsets within a tile are 16-bit)
+    for val, ok in ((32768, True), (2048, True), (65536, False), (1536, False)):
+        tb = slpic.Tuning2D()
+        tb.sort_tile = val
+        assert (L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(tb)) > 0) == ok, val
     big = slpic.run_config(workloads.sheath2d(nx=2048, ny=2048, ppc=1))
     tb = slpic.Tuning2D()
     tb.tile = 16  # 128 x 128 = 16384 blocks > 4096
