@@ -126,6 +126,24 @@ def test_sort2d_permutation_bit_exact(gpu_lib, prec, tile):
     sim.close()
 
 
+def test_sort2d_tile_size_invariance_at_full_size(gpu_lib):
+    """The 512 x 512 sheath (33.5 M particles) sorted once from its cold load
+    with 32768-slot tiles (1536 tiles) and with 2048-slot tiles (24576): the
+    stable order by key does not depend on how the slots are split, so the
+    two permutations of every slot agree bit for bit."""
+    cfg = workloads.sheath2d()
+    perms = []
+    for st in (32768, 2048):
+        print_case(f"2d full-size sort, sort_tile={st}")
+        sim = gpu_lib.Sim2D(cfg, cfg["ny"], precision="f32", sort_every=0, tile=cfg["tile"], sort_tile=st)
+        sim.sort_now()
+        perms.append([sim.perm(s) for s in range(2)])
+        sim.close()
+    for s in range(2):
+        assert len(perms[0][s]) == len(perms[1][s]) > 0
+        assert np.array_equal(perms[0][s], perms[1][s]), s
+
+
 @pytest.mark.parametrize("nx,ny", [(16, 8), (33, 64), (100, 128)])
 def test_poisson2d_matches_oracle(gpu_lib, nx, ny):
     cfg, _ = _cfg(nx=nx, ny=ny, ppc=1)
