@@ -156,7 +156,7 @@ typedef struct {
     int32_t block;        /* threads per push workgroup: 64, 128, 192 or 256, one   */
                           /* wavefront per chunk; 0 = default (128)                  */
     int32_t graph_steps;  /* steps captured per HIP graph; 0 = direct launches       */
-    int32_t sort_tile;    /* particles per sort workgroup; 0 = default               */
+    int32_t sort_tile;    /* particles per sort workgroup, at most 32768; 0 = 16384  */
     int32_t retire_steady;/* 1: a run stops advancing (push, source, field solve and */
                           /* step count frozen) from the step after its steady      */
                           /* detector flags it; 0 = every run always advances       */

@@ -162,6 +162,8 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (t.block == 0) t.block = 128;
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
     if (t.sort_tile == 0) t.sort_tile = 16384;
+    // the scatter keeps per-wave offsets within a tile's run of one key in 16 bits
+    if (t.sort_tile > 32768) return SLPIC_EINVAL;
     if (t.block < 64 || t.block > 256 || t.block % 64) return SLPIC_EINVAL;  // 1..4 push waves
     {   // one wavefront per push chunk: chunk = 64 * P, P in {1, 2, 4, 8, 16}
         const int per = t.chunk / 64;
@@ -363,6 +365,7 @@ struct Context {
     long long* btot = nullptr;
     int64_t steps_done = 0;
     size_t field_lds = 0, source_field_lds = 0, sort_lds = 0, moments_lds = 0;
+    size_t scatter_lds = 0;  // four waves' packed per-key offsets
     // threads of the per-run source + field workgroup (fewer waves helped the
     // 100-cell plates step by ~5 % but slowed the 2048-cell sheath by 10-20 %)
     int field_threads = kFieldThreads;
@@ -444,9 +447,10 @@ int do_sort(Context* c, hipStream_t s) {
         launch_zero_ints(c->a.hist, c->P.hist_entries, s);
         if (prec(c) == SLPIC_F32) launch_sort_hist_f32(c->a, nt, 256, c->sort_lds, s);
         else launch_sort_hist_f64(c->a, nt, 256, c->sort_lds, s);
+        // both sort kernels run four waves per tile: scatter_lds is sized for them
         launch_sort_scan(c->a, c->P.hist_entries, c->btot, s);
-        if (prec(c) == SLPIC_F32) launch_sort_scatter_f32(c->a, nt, 256, c->sort_lds, s);
-        else launch_sort_scatter_f64(c->a, nt, 256, c->sort_lds, s);
+        if (prec(c) == SLPIC_F32) launch_sort_scatter_f32(c->a, nt, 256, c->scatter_lds, s);
+        else launch_sort_scatter_f64(c->a, nt, 256, c->scatter_lds, s);
         launch_sort_finish(c->a, c->P.nruns, c->P.hist_entries, c->btot, s);
     });
 }
@@ -621,11 +625,12 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
     c->n_active = (int)c->P.chunks.size();
     c->btot = (long long*)(w + L.btot);
     c->field_lds = (size_t)(c->P.max_nodes + kFieldTmp) * 8;
-    c->sort_lds = (size_t)4 * c->P.max_nkeys * sizeof(int);
+    c->sort_lds = (size_t)c->P.max_nkeys * sizeof(int);  // the tile's key counts
+    c->scatter_lds = (size_t)4 * ((c->P.max_nkeys + 1) / 2) * sizeof(uint32_t);
     c->source_field_lds = c->field_lds + (size_t)2 * c->P.max_src * 8;
 
     c->moments_lds = (size_t)3 * c->P.max_nodes * 8;
-    if (c->sort_lds > 65536 || c->moments_lds > 65536 || c->source_field_lds > 65536) {
+    if (c->sort_lds > 65536 || c->scatter_lds > 65536 || c->moments_lds > 65536 || c->source_field_lds > 65536) {
         delete c;
         return SLPIC_EINVAL;
     }
