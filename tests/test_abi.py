@@ -60,6 +60,10 @@ def test_workspace_planning_validates_configs():
     tr = slpic.tuning("f32")
     tr.reserved = 1
     assert L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(tr)) == 0
+    # sort tiles of at most 32768 slots (the scatter's per-wave offsets are 16-bit)
+    for st, ok in ((32768, True), (512, True), (32769, False), (65536, False)):
+        ts = slpic.tuning("f32", sort_tile=st)
+        assert (L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(ts)) > 0) == ok, st
     inf = slpic.run_config(workloads.sheath(nx=64, ppc=10, u_over_vti=math.inf))
     assert L.slpic_workspace_bytes(ctypes.byref(inf), 1, ctypes.byref(t)) > 0
 
