@@ -105,7 +105,7 @@ def test_cold_load2d_matches_oracle(gpu_lib, prec, kind, k):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("tile", [1, 4, 5])
+@pytest.mark.parametrize("tile", [1, 4, 5, 7])  # 320, 20, 16 and 9 keys on 20 x 16 cells
 def test_sort2d_permutation_bit_exact(gpu_lib, prec, tile):
     cfg, ny = _cfg(nx=20, ny=16, ppc=10, sort_every=0)
     print_case(f"2d sort {prec} tile={tile}")
