@@ -135,7 +135,7 @@ def traffic_probe(args) -> int:
     params = launch_params(cfg, args)
     sim = slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
                     chunk=params["chunk"], block=params["block"], graph_steps=0,
-                    push_order=params.get("push_order", 0))
+                    push_order=params.get("push_order", 0), sort_tile=params.get("sort_tile", 0))
     sim.step(args.warmup)
     torch.cuda.synchronize()
     _copy_calibration()
@@ -260,7 +260,7 @@ def sweep_bench(args) -> int:
     g = max(16, params["sort_every"])
     sim = slpic.Sim(cfgs, precision=args.precision, sort_every=params["sort_every"],
                     sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"], graph_steps=g,
-              push_order=params.get("push_order", 0))
+              push_order=params.get("push_order", 0), sort_tile=params.get("sort_tile", 0))
     steps = max(g, (args.steps // g) * g)
     sim.step(g * max(1, args.warmup // g))
     torch.cuda.synchronize()
@@ -331,7 +331,7 @@ def steady_bench(args) -> int:
     block = g * max(1, 256 // g)
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
               chunk=params["chunk"], block=params["block"], graph_steps=g,
-              push_order=params.get("push_order", 0))
+              push_order=params.get("push_order", 0), sort_tile=params.get("sort_tile", 0))
     import torch
     plain = []
     # both sides on a side stream, where blocks of g steps replay as HIP graphs
@@ -384,7 +384,8 @@ def time_to_steady(args, runs: int = 256, plain_runs: int = 16, max_steps: int =
     g = max(16, params["sort_every"])
     block = g * max(1, 256 // g)
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
-              chunk=params["chunk"], block=params["block"], graph_steps=g, push_order=params.get("push_order", 0))
+              chunk=params["chunk"], block=params["block"], graph_steps=g, push_order=params.get("push_order", 0),
+              sort_tile=params.get("sort_tile", 0))
     plain = []
     with torch.cuda.stream(torch.cuda.Stream()):
         sim = slpic.Sim(cfgs, retire_steady=True, **kw)
@@ -506,7 +507,7 @@ def warm_bench(args) -> int:
     t_pred = time.perf_counter() - t_pred
     kw = dict(precision=args.precision, sort_every=params["sort_every"], sort_bucket=params["sort_bucket"],
               chunk=params["chunk"], block=params["block"], graph_steps=g,
-              push_order=params.get("push_order", 0))
+              push_order=params.get("push_order", 0), sort_tile=params.get("sort_tile", 0))
     n = len(eval_cfgs)
     W = [max(1, c["nx"] // 4) for c in eval_cfgs]
     cold = slpic.Sim(eval_cfgs, **kw)
@@ -894,7 +895,8 @@ def run_timed(cfg, args, steps, warmup, params):
     def make():
         return slpic.Sim(cfg, precision=args.precision, sort_every=params["sort_every"],
                          sort_bucket=params["sort_bucket"], chunk=params["chunk"], block=params["block"],
-                         graph_steps=g, push_order=params.get("push_order", 0))
+                         graph_steps=g, push_order=params.get("push_order", 0),
+                         sort_tile=params.get("sort_tile", 0))
     with torch.cuda.stream(torch.cuda.Stream()):
         sim = make()
         sim.step(warmup)

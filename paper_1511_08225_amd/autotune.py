@@ -1,7 +1,8 @@
 """Launch-parameter tuner for a set of runs.
 
 Chooses the push chunk (particles per wavefront), the push workgroup size,
-the sort period and the sort key bucket for a given run set by timing short
+the sort period, the sort key bucket, the push order of the species' chunks
+and the sort tile (slots per sort workgroup) for a given run set by timing short
 trials of the real step on the GPU (coordinate descent over the candidate
 lists), and caches the choice per workload signature in a JSON file so that
 later contexts over similar run sets start tuned.  The sort schedule changes
@@ -25,9 +26,10 @@ CANDIDATES = {
     "sort_every": (8, 16, 32, 64),
     "sort_bucket": (1, 2, 4),
     "push_order": (0, 1),
+    "sort_tile": (2048, 4096, 8192, 16384, 32768),
 }
-DEFAULT = {"chunk": 512, "block": 128, "sort_every": 16, "sort_bucket": 1, "push_order": 0}
-GROUPS = (("chunk", "block"), ("sort_every",), ("sort_bucket",), ("push_order",))
+DEFAULT = {"chunk": 512, "block": 128, "sort_every": 16, "sort_bucket": 1, "push_order": 0, "sort_tile": 16384}
+GROUPS = (("chunk", "block"), ("sort_every",), ("sort_bucket",), ("push_order",), ("sort_tile",))
 SWITCH_MARGIN = 0.01  # relative gain a trial needs to replace the incumbent
 CACHE_PATH = os.environ.get("SLPIC_TUNING_CACHE",
                             os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json"))
@@ -64,7 +66,7 @@ def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, 
     warmup = max(g, (warmup // g) * g)
     sim = slpic.Sim(configs, precision=precision, sort_every=se, sort_bucket=params["sort_bucket"],
                     chunk=params["chunk"], block=params["block"], graph_steps=g,
-                    push_order=params.get("push_order", 0))
+                    push_order=params.get("push_order", 0), sort_tile=params.get("sort_tile", 0))
     try:
         sim.step(warmup)
         torch.cuda.synchronize()

@@ -72,7 +72,8 @@ def collect_profiles(cfgs: list[dict], steps: int, sample_every: int = 64, sampl
     se = tuning["sort_every"]
     g = max(16, se)
     sim = slpic.Sim(cfgs, precision=precision, sort_every=se, sort_bucket=tuning["sort_bucket"],
-                    chunk=tuning["chunk"], block=tuning["block"], graph_steps=g)
+                    chunk=tuning["chunk"], block=tuning["block"], graph_steps=g,
+                    push_order=tuning.get("push_order", 0), sort_tile=tuning.get("sort_tile", 0))
     first = max(0, steps - sample_last)
     sim.step(first)
     done = first

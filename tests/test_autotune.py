@@ -28,7 +28,7 @@ def test_signature_groups_similar_run_sets():
 
 def test_coordinate_descent_finds_separable_optimum_and_caches(tmp_path):
     cfgs = workloads.batched_sweep(nruns=4, seed=3, cells_range=(64, 128), ppc_range=(20, 40))
-    opt = {"chunk": 256, "block": 256, "sort_every": 32, "sort_bucket": 2, "push_order": 1}
+    opt = {"chunk": 256, "block": 256, "sort_every": 32, "sort_bucket": 2, "push_order": 1, "sort_tile": 8192}
     path = str(tmp_path / "cache.json")
     got = autotune.tune(cfgs, "f32", cache_path=path, measure_fn=_cost(opt))
     assert got == opt
@@ -37,7 +37,7 @@ def test_coordinate_descent_finds_separable_optimum_and_caches(tmp_path):
     assert cache[key]["params"] == opt
     nc = len(autotune.CANDIDATES["chunk"]) * len(autotune.CANDIDATES["block"])
     # the default, its (chunk, block) group, then one new trial per other value
-    assert len(cache[key]["trials"]) == 1 + (nc - 1) + (4 - 1) + (3 - 1) + (2 - 1)
+    assert len(cache[key]["trials"]) == 1 + (nc - 1) + (4 - 1) + (3 - 1) + (2 - 1) + (5 - 1)
     # a cached key is returned without measuring
     def boom(*a):
         raise AssertionError("measured a cached signature")
@@ -45,8 +45,8 @@ def test_coordinate_descent_finds_separable_optimum_and_caches(tmp_path):
 
 
 def test_entry_without_a_newer_parameter_is_extended(tmp_path):
-    """A cached entry lacking a parameter (tuned before it existed) keeps its
-    values; only the missing group is searched, from its best."""
+    """A cached entry lacking parameters (tuned before they existed) keeps its
+    values; only the missing groups are searched, from its best."""
     cfgs = workloads.batched_sweep(nruns=4, seed=3, cells_range=(64, 128), ppc_range=(20, 40))
     key = autotune.signature(cfgs, "f32")
     old = {"chunk": 1024, "block": 64, "sort_every": 64, "sort_bucket": 4}
@@ -54,7 +54,7 @@ def test_entry_without_a_newer_parameter_is_extended(tmp_path):
     json.dump({key: {"params": old, "ps_per_push": 5.0, "trials": [{"params": old, "ps_per_push": 5.0}]}},
               open(path, "w"))
     seen = []
-    opt = dict(old, push_order=1)
+    opt = dict(old, push_order=1, sort_tile=32768)
     cost = _cost(opt)
 
     def measure(c, p, params, s, w):
@@ -62,7 +62,9 @@ def test_entry_without_a_newer_parameter_is_extended(tmp_path):
         return cost(c, p, params, s, w)
     got = autotune.tune(cfgs, "f32", cache_path=path, measure_fn=measure)
     assert got == opt
-    assert seen == [dict(old, push_order=0), opt]
+    start = dict(old, push_order=0, sort_tile=16384)
+    assert seen == [start, dict(start, push_order=1),
+                    *[dict(start, push_order=1, sort_tile=t) for t in (2048, 4096, 8192, 32768)]]
     rec = json.load(open(path))[key]
     assert rec["params"] == opt and rec["earlier_trials"] == [{"params": old, "ps_per_push": 5.0}]
     assert rec["ps_per_push"] == min(t["ps_per_push"] for t in rec["trials"])
