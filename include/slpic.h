@@ -165,7 +165,10 @@ typedef struct {
                           /* the two species' chunks interleaved (by first slot).   */
                           /* Results do not depend on it (but for the order of the  */
                           /* charge atomics); the faster one depends on the size.   */
-    int32_t reserved;     /* must be 0 (SLPIC_EINVAL otherwise)                     */
+    int32_t record_perm;  /* 1: every sort also stores its permutation for         */
+                          /* slpic_export_perm; 0 = not stored (the scatter writes */
+                          /* the particles only, 4 B per particle less) and        */
+                          /* slpic_export_perm returns SLPIC_EINVAL                 */
 } slpic_tuning;
 
 typedef struct {
@@ -306,7 +309,8 @@ int slpic_export_grid(void* ctx, int32_t run, double* h_Q, double* h_phi, double
 int slpic_sort_now(void* ctx, void* stream);
 
 /* Sync.  The permutation of the last sort of (run, species): h_perm[new] =
- * old slot, *n entries (capacity on entry, count on return). */
+ * old slot, *n entries (capacity on entry, count on return).  Only in a
+ * context whose tuning has record_perm = 1 (SLPIC_EINVAL otherwise). */
 int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, int64_t* n);
 
 /* Kernel timing with HIP events on the launch stream (for roofline

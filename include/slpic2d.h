@@ -58,6 +58,9 @@ typedef struct {
                          /* blocks of this many steps as one HIP graph (rounded  */
                          /* up to a multiple of sort_every; the graph is         */
                          /* captured on first use); 0 = direct launches          */
+    int32_t record_perm; /* 1: every sort also stores its permutation for        */
+                         /* slpic2d_export_perm (4 B per slot of workspace); 0 = */
+                         /* not stored, slpic2d_export_perm returns SLPIC_EINVAL */
 } slpic2d_tuning;
 
 typedef struct {

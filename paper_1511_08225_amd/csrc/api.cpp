@@ -157,7 +157,7 @@ int make_plan(const slpic_run_config* cfg, int nruns, const slpic_tuning* tin, P
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
     if (t.sort_every < 0 || t.sort_bucket < 0 || t.chunk < 0 || t.block < 0 || t.graph_steps < 0 ||
         t.sort_tile < 0 || (t.retire_steady != 0 && t.retire_steady != 1) ||
-        (t.push_order != 0 && t.push_order != 1) || t.reserved != 0)
+        (t.push_order != 0 && t.push_order != 1) || (t.record_perm != 0 && t.record_perm != 1))
         return SLPIC_EINVAL;
     if (t.block == 0) t.block = 128;
     if (t.chunk == 0) t.chunk = 64 * (t.precision == SLPIC_F32 ? 8 : 4);
@@ -606,6 +606,7 @@ int slpic_init(const slpic_run_config* runs, int32_t nruns, const slpic_tuning* 
         a.bufs.vp2[b] = w + L.vp2[b];
     }
     a.perm = (int32_t*)(w + L.perm);
+    a.sort_perm = c->P.tun.record_perm ? a.perm : nullptr;
     a.E = (double*)(w + L.E);
     a.E32 = (float*)(w + L.E32);
     a.phi = (double*)(w + L.phi);
@@ -1041,7 +1042,8 @@ int slpic_sort_now(void* ctx, void* stream) {
 
 int slpic_export_perm(void* ctx, int32_t run, int32_t species, int32_t* h_perm, int64_t* n) {
     Context* c = ctx_of(ctx);
-    if (!c || !n || run < 0 || run >= c->P.nruns || species < 0 || species > 1) return SLPIC_EINVAL;
+    if (!c || !n || run < 0 || run >= c->P.nruns || species < 0 || species > 1 || !c->P.tun.record_perm)
+        return SLPIC_EINVAL;
     HIP_TRY(hipDeviceSynchronize());
     RunState st;
     if (int rc = copy_d2h(&st, c->a.state + run, sizeof st)) return rc;

@@ -54,7 +54,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
     if (tin) t = *tin;
     if (t.precision != SLPIC_F32 && t.precision != SLPIC_F64) return SLPIC_EINVAL;
     if (t.sort_every < 0 || t.tile < 0 || t.margin < 0 || t.per_thread < 0 || t.tail_groups < 0 || t.sort_tile < 0 ||
-        t.graph_steps < 0)
+        t.graph_steps < 0 || (t.record_perm != 0 && t.record_perm != 1))
         return SLPIC_EINVAL;
     // a captured block of steps starts at a multiple of the sort period
     if (t.sort_every > 0 && t.graph_steps > 0 && t.graph_steps % t.sort_every)
@@ -159,7 +159,7 @@ int make_plan2(const slpic_run_config* c, int ny, const slpic2d_tuning* tin, Pla
         L.vy[b] = take(tsz * P.total_slots);
         L.vz2[b] = take(tsz * P.total_slots);
     }
-    L.perm = take(sizeof(int32_t) * P.total_slots);
+    L.perm = take(t.record_perm ? sizeof(int32_t) * P.total_slots : 0);
     L.Q = take(sizeof(double) * 2 * R.nodes);
     L.phi = take(sizeof(double) * R.nodes);
     L.E = take(sizeof(double2) * R.nodes);
@@ -349,7 +349,7 @@ int slpic2d_init(const slpic_run_config* run, int32_t ny, const slpic2d_tuning* 
         a.vy[b] = w + L.vy[b];
         a.vz2[b] = w + L.vz2[b];
     }
-    a.perm = (int32_t*)(w + L.perm);
+    a.perm = c->P.tun.record_perm ? (int32_t*)(w + L.perm) : nullptr;
     a.Q = (double*)(w + L.Q);
     a.phi = (double*)(w + L.phi);
     a.E = (double2*)(w + L.E);
@@ -617,7 +617,7 @@ int slpic2d_sort_now(void* ctx, void* stream) {
 
 int slpic2d_export_perm(void* ctx, int32_t species, int32_t* h_perm, int64_t* n) {
     Ctx2* c = ctx2(ctx);
-    if (!c || species < 0 || species > 1 || !n || !h_perm) return SLPIC_EINVAL;
+    if (!c || species < 0 || species > 1 || !n || !h_perm || !c->a.perm) return SLPIC_EINVAL;
     HIP2_TRY(hipDeviceSynchronize());
     State2D st;
     int rc = read_state(c, st);

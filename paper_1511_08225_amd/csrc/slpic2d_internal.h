@@ -81,7 +81,8 @@ struct Args2D {
     const double2* tw;   // exp(-2 pi i k / ny), k < ny/2
     int* hist;       // sort histograms [species][key][slot tile]
     long long* btot; // scan block totals
-    int32_t* perm;   // last sort's permutation (new slot -> old slot), per species at poff
+    int32_t* perm;   // last sort's permutation (new slot -> old slot), per species at poff; null
+                     // unless sorts record it
     int64_t* tbeg;   // tile slot ranges after the last sort [2][nkeys + 1]
     int2* counts;    // [2][kCountSlots2]: (absorbed, pushed) of the last push
     Inject2D* inj;

@@ -151,7 +151,8 @@ struct KArgs {
     int64_t* totals;      // live slots after the sort [run][species]
     int2* counts;         // [run][species][kCountSlots]: (absorbed, pushed) of the last push
     int* push_err;        // [run]: error flags raised by the last push
-    int32_t* perm;        // last sort's permutation (new slot -> old slot)
+    int32_t* perm;        // last sort's permutation (new slot -> old slot); scratch of a limit change
+    int32_t* sort_perm;   // perm when sorts record their permutation, else null
     double* Macc;         // moment window accumulators [run]: 7 rows of nodes at 7*goff
     const int4* injb;     // plates: wall-injection workgroups (run, species, first particle, 0)
     int32_t ninjb;        // their count (0 without plates runs)

@@ -50,7 +50,7 @@ class Tuning(ctypes.Structure):
                 ("sort_bucket", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
                 ("sort_tile", ctypes.c_int32), ("retire_steady", ctypes.c_int32),
-                ("push_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("push_order", ctypes.c_int32), ("record_perm", ctypes.c_int32)]
 
 
 class RunStatus(ctypes.Structure):
@@ -83,7 +83,7 @@ class WaveConfig(ctypes.Structure):
 class Tuning2D(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("margin", ctypes.c_int32), ("per_thread", ctypes.c_int32), ("tail_groups", ctypes.c_int32),
-                ("sort_tile", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+                ("sort_tile", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("record_perm", ctypes.c_int32)]
 
 
 class Status2D(ctypes.Structure):
@@ -230,13 +230,14 @@ def run_config(cfg: dict) -> RunConfig:
 
 
 def tuning(precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0, graph_steps=0,
-           sort_tile=0, retire_steady=False, push_order=0) -> Tuning:
+           sort_tile=0, retire_steady=False, push_order=0, record_perm=False) -> Tuning:
     t = Tuning()
     t.precision = {"f32": SLPIC_F32, "f64": SLPIC_F64}[precision] if isinstance(precision, str) else int(precision)
     t.sort_every, t.sort_bucket, t.chunk, t.block = int(sort_every), int(sort_bucket), int(chunk), int(block)
     t.graph_steps, t.sort_tile = int(graph_steps), int(sort_tile)
     t.retire_steady = int(bool(retire_steady))
     t.push_order = int(push_order)
+    t.record_perm = int(bool(record_perm))
     return t
 
 
@@ -266,11 +267,13 @@ class Sim:
     """One or more independent 1D3V sheaths advanced together on one GPU."""
 
     def __init__(self, configs, precision="f32", sort_every=16, sort_bucket=1, chunk=0, block=0,
-                 graph_steps=0, sort_tile=0, device="cuda", warm=None, retire_steady=False, push_order=0):
+                 graph_steps=0, sort_tile=0, device="cuda", warm=None, retire_steady=False, push_order=0,
+                 record_perm=False):
         """warm: optional list (one entry per run) of None or a (7, 256)
         array of predicted profiles (phi, n_e, n_i, Gamma_e, Gamma_i, T_e,
         T_i on x/L = k/255; a (5, 256) array loads at the source
-        temperatures) for a warm load instead of the cold one."""
+        temperatures) for a warm load instead of the cold one.
+        record_perm: every sort also stores its permutation (for perm())."""
         if isinstance(configs, dict):
             configs = [configs]
         self.configs = [dict(c) for c in configs]
@@ -294,7 +297,7 @@ class Sim:
                 self._warm.append(a)
                 self._cfg[r].warm_profile = a.ctypes.data
         self._tun = tuning(precision, sort_every, sort_bucket, chunk, block, graph_steps, sort_tile, retire_steady,
-                           push_order)
+                           push_order, record_perm)
         L = lib()
         nbytes = L.slpic_workspace_bytes(self._cfg, self.nruns, ctypes.byref(self._tun))
         if nbytes == 0:
@@ -386,6 +389,8 @@ class Sim:
         return {"Q": Q.reshape(2, nodes), "phi": phi, "E": E}
 
     def perm(self, run: int, species: int) -> np.ndarray:
+        if not self._tun.record_perm:
+            raise SlpicError("sort permutations are recorded only with record_perm=True")
         n = ctypes.c_int64(0)
         lib().slpic_export_perm(self._ctx, run, species, None, ctypes.byref(n))
         p = np.zeros(max(n.value, 1), dtype=np.int32)
@@ -546,7 +551,7 @@ class Sim2D:
     """One 2D3V sheath (y periodic over ny cells, dy = dx) on one GPU."""
 
     def __init__(self, config: dict, ny: int, precision="f32", sort_every=8, tile=8, margin=0, per_thread=0,
-                 tail_groups=0, sort_tile=0, graph_steps=0, device="cuda"):
+                 tail_groups=0, sort_tile=0, graph_steps=0, device="cuda", record_perm=False):
         self.config = dict(config)
         self.nx, self.ny = int(config["nx"]), int(ny)
         self.precision = precision
@@ -556,6 +561,7 @@ class Sim2D:
         t.sort_every, t.tile, t.margin = int(sort_every), int(tile), int(margin)
         t.per_thread, t.tail_groups, t.sort_tile = int(per_thread), int(tail_groups), int(sort_tile)
         t.graph_steps = int(graph_steps)
+        t.record_perm = int(bool(record_perm))
         self._tun = t
         L = lib()
         nbytes = L.slpic2d_workspace_bytes(ctypes.byref(self._cfg), self.ny, ctypes.byref(t))
@@ -630,6 +636,8 @@ class Sim2D:
         _check(lib().slpic2d_set_counters(self._ctx, int(step), float(acc_e)), "slpic2d_set_counters")
 
     def perm(self, species: int) -> np.ndarray:
+        if not self._tun.record_perm:
+            raise SlpicError("sort permutations are recorded only with record_perm=True")
         cnt = max(self.status()["capacity"][species], 1)
         p = np.zeros(cnt, dtype=np.int32)
         n = ctypes.c_int64(cnt)

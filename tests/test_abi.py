@@ -57,9 +57,12 @@ def test_workspace_planning_validates_configs():
     for order, ok in ((0, True), (1, True), (2, False), (-1, False)):
         to = slpic.tuning("f32", push_order=order)
         assert (L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(to)) > 0) == ok, order
-    tr = slpic.tuning("f32")
-    tr.reserved = 1
-    assert L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(tr)) == 0
+    # recording the sort permutation: 0 or 1 (the buffer is kept either way: a
+    # speed-limit change uses it)
+    for rp, ok in ((0, True), (1, True), (2, False), (-1, False)):
+        tr = slpic.tuning("f32")
+        tr.record_perm = rp
+        assert (L.slpic_workspace_bytes(ctypes.byref(good), 1, ctypes.byref(tr)) > 0) == ok, rp
     # sort tiles of at most 32768 slots (the scatter's per-wave offsets are 16-bit)
     for st, ok in ((32768, True), (512, True), (32769, False), (65536, False)):
         ts = slpic.tuning("f32", sort_tile=st)
@@ -123,6 +126,14 @@ def test_2d_workspace_planning_validates_configs():
     tb = slpic.Tuning2D()
     tb.tile = 16  # 128 x 128 = 16384 blocks > 4096
     assert L.slpic2d_workspace_bytes(ctypes.byref(big), 2048, ctypes.byref(tb)) == 0
+    # the sort permutation: 0 or 1, and its 4 B per slot only when recorded
+    for rp, ok in ((0, True), (1, True), (2, False)):
+        tb = slpic.Tuning2D()
+        tb.record_perm = rp
+        assert (L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(tb)) > 0) == ok, rp
+    tb = slpic.Tuning2D()
+    tb.record_perm = 1
+    assert L.slpic2d_workspace_bytes(ctypes.byref(good), 64, ctypes.byref(tb)) >= n + 4 * 64 * 64 * 4 * 2
     # F64 needs more bytes than F32
     t64 = slpic.Tuning2D()
     t64.precision = slpic.SLPIC_F64

@@ -8,6 +8,7 @@ positions, float velocities), within 1e-5; cell indices and sort
 permutations bit-exact where the oracle position is not within rounding of a
 cell edge (FP64) or on identical stored positions (sort).
 """
+import ctypes
 import math
 
 import numpy as np
@@ -265,7 +266,7 @@ def test_sort_permutation_bit_exact(gpu_lib, prec, bucket, sort_tile):
     run = oracle.Run(cfg)
     run.step(40)  # dead slots and appended injections in place
     print_case(f"sort {prec} bucket={bucket} sort_tile={sort_tile}")
-    sim = gpu_lib.Sim(cfg, precision=prec, sort_every=0, sort_bucket=bucket, sort_tile=sort_tile)
+    sim = gpu_lib.Sim(cfg, precision=prec, sort_every=0, sort_bucket=bucket, sort_tile=sort_tile, record_perm=True)
     push_oracle_to_gpu(sim, 0, run, quantize=(prec == "f32"))
     before = [oracle_state(run, s) for s in range(2)]
     assert any((b[0] < 0).any() for b in before)
@@ -280,6 +281,41 @@ def test_sort_permutation_bit_exact(gpu_lib, prec, bucket, sort_tile):
         assert np.array_equal(vxg, vxo)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_sort_without_permutation_record(gpu_lib, prec):
+    """By default a sort stores no permutation.  From the same imported state
+    (live slots over five 2048-slot sort tiles) the sorted particles are bit
+    for bit the oracle's stable sort, as in a context that records the
+    permutation; exporting it is refused."""
+    cfg = workloads.small_sheath(sort_every=0, sort_bucket=1, seed=6)
+    run = oracle.Run(cfg)
+    run.step(40)  # dead slots and appended injections in place
+    print_case(f"sort without permutation record, {prec}")
+    sims = [gpu_lib.Sim(cfg, precision=prec, sort_every=0, sort_bucket=1, sort_tile=2048, record_perm=r)
+            for r in (False, True)]
+    for sim in sims:
+        push_oracle_to_gpu(sim, 0, run, quantize=(prec == "f32"))
+        sim.sort_now()
+    run.sort()
+    for s in range(2):
+        xo, vxo, _ = oracle_state(run, s)
+        assert len(xo) > 2048
+        g0, g1 = sims[0].export_particles(0, s), sims[1].export_particles(0, s)
+        assert np.array_equal(g0[0], xo) and np.array_equal(g0[1], vxo), s
+        for u, v in zip(g0, g1):
+            assert np.array_equal(u, v), s
+    with pytest.raises(gpu_lib.SlpicError):
+        sims[0].perm(0, 0)
+    n = ctypes.c_int64(1 << 16)
+    buf = np.zeros(1 << 16, dtype=np.int32)
+    rc = gpu_lib.lib().slpic_export_perm(sims[0]._ctx, 0, 0, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         ctypes.byref(n))
+    assert rc == -1
+    assert len(sims[1].perm(0, 0)) == sims[1].status(0)["nslots"][0]
+    for sim in sims:
+        sim.close()
+
+
 @pytest.mark.parametrize("bucket", [1, 4])
 def test_sort_permutation_production_size(gpu_lib, bucket):
     """The production sheath (4,096,000 particles, 3,072,000 slots per species:
@@ -288,7 +324,8 @@ def test_sort_permutation_production_size(gpu_lib, bucket):
     bit-exact against the oracle's stable sort of the GPU's own positions."""
     cfg = workloads.production_sheath(u_over_vti=2.0, sort_every=0, sort_bucket=bucket)
     print_case(f"production-size sort, bucket {bucket}: 24 steps")
-    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=0, sort_bucket=bucket, chunk=512, block=64, push_order=1)
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=0, sort_bucket=bucket, chunk=512, block=64, push_order=1,
+                      record_perm=True)
     sim.step(24)
     run = oracle.Run(cfg, load=False)
     before = []

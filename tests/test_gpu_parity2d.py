@@ -109,7 +109,7 @@ def test_cold_load2d_matches_oracle(gpu_lib, prec, kind, k):
 def test_sort2d_permutation_bit_exact(gpu_lib, prec, tile):
     cfg, ny = _cfg(nx=20, ny=16, ppc=10, sort_every=0)
     print_case(f"2d sort {prec} tile={tile}")
-    sim = gpu_lib.Sim2D(cfg, ny, precision=prec, sort_every=0, tile=tile)
+    sim = gpu_lib.Sim2D(cfg, ny, precision=prec, sort_every=0, tile=tile, record_perm=True)
     run = oracle.Run2D(cfg, ny, tile=tile)
     run.step(3)  # some absorbed (dead) slots and appended source particles
     _push_to_gpu(sim, run, quantize=(prec == "f32"))
@@ -126,6 +126,38 @@ def test_sort2d_permutation_bit_exact(gpu_lib, prec, tile):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_sort2d_without_permutation_record(gpu_lib, prec):
+    """By default a 2D sort stores no permutation (and its workspace holds
+    none).  From the same imported state (live slots over three 1024-slot
+    sort tiles) the sorted particles are bit for bit the oracle's stable
+    sort, as in a context that records the permutation; exporting it is
+    refused."""
+    cfg, ny = _cfg(nx=24, ny=16, ppc=8, sort_every=0)
+    run = oracle.Run2D(cfg, ny, tile=4)
+    run.step(3)  # some absorbed (dead) slots and appended source particles
+    print_case(f"2d sort without permutation record, {prec}")
+    sims = [gpu_lib.Sim2D(cfg, ny, precision=prec, sort_every=0, tile=4, sort_tile=1024, record_perm=r)
+            for r in (False, True)]
+    assert sims[0].workspace.numel() < sims[1].workspace.numel()
+    for sim in sims:
+        _push_to_gpu(sim, run, quantize=(prec == "f32"))
+        sim.sort_now()
+    run.sort()
+    for s in range(2):
+        o = _state(run, s)
+        assert len(o[0]) > 2 * 1024
+        g0, g1 = sims[0].export_particles(s), sims[1].export_particles(s)
+        assert np.array_equal(g0[0], o[0]) and np.array_equal(g0[1], o[1]), s
+        for u, v in zip(g0, g1):
+            assert np.array_equal(u, v), s
+    with pytest.raises(gpu_lib.SlpicError):
+        sims[0].perm(0)
+    assert len(sims[1].perm(0)) == sims[1].status()["nslots"][0]
+    for sim in sims:
+        sim.close()
+
+
 def test_sort2d_tile_size_invariance_at_full_size(gpu_lib):
     """The 512 x 512 sheath (33.5 M particles) sorted once from its cold load
     with 32768-slot tiles (1536 tiles) and with 2048-slot tiles (24576): the
@@ -135,7 +167,8 @@ def test_sort2d_tile_size_invariance_at_full_size(gpu_lib):
     perms = []
     for st in (32768, 2048):
         print_case(f"2d full-size sort, sort_tile={st}")
-        sim = gpu_lib.Sim2D(cfg, cfg["ny"], precision="f32", sort_every=0, tile=cfg["tile"], sort_tile=st)
+        sim = gpu_lib.Sim2D(cfg, cfg["ny"], precision="f32", sort_every=0, tile=cfg["tile"], sort_tile=st,
+                            record_perm=True)
         sim.sort_now()
         perms.append([sim.perm(s) for s in range(2)])
         sim.close()
@@ -313,7 +346,8 @@ def test_full_size_2d_f32_sampled_and_properties(gpu_lib):
     cfg = workloads.sheath2d()
     nx, ny = cfg["nx"], cfg["ny"]
     print_case("2d full size: init (512 x 512 cells, 64 ppc per species)")
-    sim = gpu_lib.Sim2D(cfg, ny, precision="f32", sort_every=cfg["sort_every"], tile=cfg["tile"])
+    # the benchmark's launch configuration, with the sort permutation recorded
+    sim = gpu_lib.Sim2D(cfg, ny, precision="f32", sort_every=cfg["sort_every"], tile=cfg["tile"], record_perm=True)
     st = sim.status()
     fb = st["fixed_bits"]
     assert st["nslots"] == [nx * ny * 64] * 2 and st["nsorted"] == st["nslots"]
