@@ -82,6 +82,15 @@ def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, 
     return math.inf if flagged else dt / max(pushes, 1)
 
 
+def cached(configs: list[dict], precision: str = "f32", cache_path: str = CACHE_PATH) -> dict | None:
+    """The cached parameters of this run set's signature (complete entries
+    only), without measuring anything; None if there are none."""
+    entry = _load_cache(cache_path).get(signature(configs, precision))
+    if entry and all(k in entry["params"] for k in DEFAULT):
+        return dict(entry["params"])
+    return None
+
+
 def tune(configs: list[dict], precision: str = "f32", cache_path: str = CACHE_PATH, force: bool = False,
          steps: int = 64, warmup: int = 32, log=None, measure_fn=None) -> dict:
     """Best parameters for this run set (cached by signature).  measure_fn

@@ -30,6 +30,15 @@ def set_oracle_particles(run: "oracle.Run", s: int, x, vx, vp2):
     run.set_particles(s, x, vx, np.sqrt(vp2), np.zeros_like(vp2))
 
 
+def bench_launch(cfg: dict, precision: str = "f32") -> dict:
+    """The launch parameters the benchmark runs this workload with: the
+    autotuner's committed cache entry for its signature (no measuring)."""
+    from paper_1511_08225_amd import autotune
+    p = autotune.cached([cfg], precision)
+    assert p is not None, "no tuned launch cached for " + autotune.signature([cfg], precision)
+    return p
+
+
 def push_oracle_to_gpu(sim, r: int, run: "oracle.Run", quantize: bool):
     st = sim.status(r)
     for s in range(2):

@@ -38,6 +38,8 @@ def test_coordinate_descent_finds_separable_optimum_and_caches(tmp_path):
     nc = len(autotune.CANDIDATES["chunk"]) * len(autotune.CANDIDATES["block"])
     # the default, its (chunk, block) group, then one new trial per other value
     assert len(cache[key]["trials"]) == 1 + (nc - 1) + (4 - 1) + (3 - 1) + (2 - 1) + (5 - 1)
+    assert autotune.cached(cfgs, "f32", cache_path=path) == opt
+    assert autotune.cached(cfgs, "f64", cache_path=path) is None
     # a cached key is returned without measuring
     def boom(*a):
         raise AssertionError("measured a cached signature")

@@ -12,7 +12,8 @@ import pytest
 
 import oracle
 import workloads
-from parity_util import cells_agree, oracle_state, print_case, push_oracle_to_gpu, quantize_for_f32, rel_inf
+from parity_util import (bench_launch, cells_agree, oracle_state, print_case, push_oracle_to_gpu, quantize_for_f32,
+                         rel_inf)
 
 pytestmark = pytest.mark.gpu
 
@@ -131,12 +132,15 @@ def test_one_step_f32_developed_sheath(gpu_lib):
 
 def test_one_step_f32_production_size(gpu_lib):
     """2048 cells, 1000 per cell per species, u = 2 v_ti with a profile from
-    0.4 to 1.6 times it, in the benchmark's launch configuration."""
+    0.4 to 1.6 times it, in the push launch the benchmark tunes for the
+    uniform limit (the autotuner's cached chunk, workgroup and order)."""
     cfg = workloads.production_sheath(u_over_vti=2.0, sort_every=16)
     cfg["limit_profile"] = _profile(cfg["nx"], cfg["u"], phase=1.3)
     print_case("limit profile f32 production size: oracle load")
     run = oracle.Run(dict(cfg, sort_every=1))
-    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16, chunk=512, block=64, push_order=1)
+    p = bench_launch(workloads.production_sheath(u_over_vti=2.0))
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16, chunk=p["chunk"], block=p["block"],
+                      push_order=p["push_order"])
     push_oracle_to_gpu(sim, 0, run, quantize=True)
     for k in range(2):
         print_case(f"limit profile f32 production size step {k}")

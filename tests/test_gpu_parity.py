@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import workloads
-from parity_util import (cells_agree, oracle_state, print_case, push_oracle_to_gpu, quantize_for_f32,
+from parity_util import (bench_launch, cells_agree, oracle_state, print_case, push_oracle_to_gpu, quantize_for_f32,
                          rel_inf, set_oracle_particles)
 
 pytestmark = pytest.mark.gpu
@@ -229,16 +229,20 @@ def test_one_step_f32_developed_sheath(gpu_lib, u_over_vti):
         assert fb >= 19
 
 
-@pytest.mark.parametrize("u_over_vti,push_order", [(2.0, 0), (2.0, 1), (5.0, 1), (10.0, 1), (math.inf, 1)])
-def test_one_step_f32_production_size(gpu_lib, u_over_vti, push_order):
+@pytest.mark.parametrize("u_over_vti,other_order", [(2.0, False), (2.0, True), (5.0, False), (10.0, False),
+                                                   (math.inf, False)])
+def test_one_step_f32_production_size(gpu_lib, u_over_vti, other_order):
     """2048 cells, 1000 per cell per species (4,096,000 particles), every
     speed limit of the production sweep u in {2, 5, 10, inf} v_ti (inf: the
-    PIC step dx/(5 v_te)), in the benchmark's launch configuration (either
-    push order at u = 2 v_ti)."""
+    PIC step dx/(5 v_te)), in the benchmark's launch configuration for that
+    limit (the autotuner's cached push chunk and workgroup; at u = 2 v_ti
+    also with the other push order)."""
     cfg = workloads.production_sheath(u_over_vti=u_over_vti, sort_every=16)
-    print_case(f"f32 production size, u/vti={u_over_vti}, push order {push_order}: oracle load")
+    p = bench_launch(cfg)
+    order = 1 - p["push_order"] if other_order else p["push_order"]
+    print_case(f"f32 production size, u/vti={u_over_vti}, launch {p}, push order {order}: oracle load")
     run = oracle.Run(dict(cfg, sort_every=1))
-    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16, chunk=512, block=64, push_order=push_order)
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=16, chunk=p["chunk"], block=p["block"], push_order=order)
     push_oracle_to_gpu(sim, 0, run, quantize=True)
     for k in range(2):
         print_case(f"f32 production size step {k}")
@@ -281,6 +285,64 @@ def test_sort_permutation_bit_exact(gpu_lib, prec, bucket, sort_tile):
         assert np.array_equal(vxg, vxo)
 
 
+def test_ten_times_ppc_sampled_step(gpu_lib):
+    """The 10x-ppc production sheath (10,000 per cell per species, 40,960,000
+    particles) in the benchmark's launch configuration for it (the
+    autotuner's cached launch: 16 particles per lane): after 40 steps, one
+    step recomputed for 300 sampled particles per species by the oracle's
+    exact velocity map from the GPU's own node field (Eq. A2a-b), and the
+    charge identity Q = q w sum beta over the live particles (Eq. A2c)."""
+    cfg = workloads.production_sheath(u_over_vti=2.0, ppc=10000)
+    p = bench_launch(cfg)
+    print_case(f"10x production size: load and 40 steps, launch {p}")
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=p["sort_every"], sort_bucket=p["sort_bucket"],
+                      chunk=p["chunk"], block=p["block"], push_order=p["push_order"], sort_tile=p["sort_tile"])
+    sim.step(40)  # no sort falls in step 41 (sorts end every 64th step): slots keep their particles
+    assert sim.status(0)["nslots"][0] > 20_000_000
+    g0 = sim.grid(0)
+    before = [sim.export_particles(0, s) for s in range(2)]
+    print_case("10x production size: one step")
+    sim.step(1)
+    g1 = sim.grid(0)
+    nx, u, dt, dtdx = cfg["nx"], cfg["u"], cfg["dt"], cfg["dt"] / cfg["dx"]
+    rng = np.random.default_rng(5)
+    for s in range(2):
+        X0, VX0, VP0 = before[s]
+        X, VX, VP = sim.export_particles(0, s)
+        qm = cfg["species"][s]["charge"] / cfg["species"][s]["mass"]
+        vs = np.abs(VX0).max()
+        checked = 0
+        for d in rng.integers(0, len(X0), 300):
+            if X0[d] < 0:
+                continue
+            c = int(X0[d])
+            f = X0[d] - c
+            e = g0["E"][c] * (1 - f) + g0["E"][c + 1] * f
+            v1 = oracle.kick_exact("step", u, dt, [VX0[d], math.sqrt(VP0[d]), 0.0], [qm * e, 0.0, 0.0])
+            sp = math.sqrt(v1 @ v1)
+            b = 1.0 if sp <= u else u / sp
+            xn = X0[d] + b * v1[0] * dtdx
+            if xn < 0:  # symmetry plane: specular
+                xn, v1[0] = -xn, -v1[0]
+            if abs(xn - nx) < 1e-4:  # within rounding of the wall: either side is right
+                continue
+            if xn >= nx:
+                assert X[d] < 0, (s, d)
+                continue
+            assert abs(X[d] - xn) <= 1e-5, (s, d, X[d], xn)
+            assert abs(VX[d] - v1[0]) <= 1e-5 * vs, (s, d, VX[d], v1[0])
+            assert VP[d] == VP0[d]  # v_perp^2 is invariant in 1D
+            checked += 1
+        assert checked >= 250, checked
+        live = X >= 0
+        s2 = VX[live] ** 2 + VP[live]
+        beta = np.where(s2 <= u * u, 1.0, u / np.sqrt(np.maximum(s2, 1e-300)))
+        want = cfg["species"][s]["charge"] * sim.status(0)["weight"][s] * beta.sum()
+        assert g1["Q"][s].sum() == pytest.approx(want, rel=1e-9), s
+    assert sim.status(0)["error_flags"] == 0
+    sim.close()
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_sort_without_permutation_record(gpu_lib, prec):
     """By default a sort stores no permutation.  From the same imported state
@@ -316,16 +378,21 @@ def test_sort_without_permutation_record(gpu_lib, prec):
         sim.close()
 
 
-@pytest.mark.parametrize("bucket", [1, 4])
-def test_sort_permutation_production_size(gpu_lib, bucket):
-    """The production sheath (4,096,000 particles, 3,072,000 slots per species:
-    188 sort tiles of 16384 slots each) sorted after 24 unsorted steps, in the
-    benchmark's launch configuration: permutation and sorted particles
-    bit-exact against the oracle's stable sort of the GPU's own positions."""
+@pytest.mark.parametrize("bucket,sort_tile", [(None, None), (4, 16384), (1, 16384)])
+def test_sort_permutation_production_size(gpu_lib, bucket, sort_tile):
+    """The production sheath (4,096,000 particles, 3,072,000 slots per species)
+    sorted after 24 unsorted steps, in the benchmark's launch configuration
+    (the autotuner's cached bucket and sort tile: 1500 tiles of 2048 slots
+    per species), and with 188 tiles of 16384 slots at buckets 4 and 1:
+    permutation and sorted particles bit-exact against the oracle's stable
+    sort of the GPU's own positions."""
+    p = bench_launch(workloads.production_sheath(u_over_vti=2.0))
+    bucket = p["sort_bucket"] if bucket is None else bucket
+    sort_tile = p["sort_tile"] if sort_tile is None else sort_tile
     cfg = workloads.production_sheath(u_over_vti=2.0, sort_every=0, sort_bucket=bucket)
-    print_case(f"production-size sort, bucket {bucket}: 24 steps")
-    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=0, sort_bucket=bucket, chunk=512, block=64, push_order=1,
-                      record_perm=True)
+    print_case(f"production-size sort, bucket {bucket}, sort tile {sort_tile}: 24 steps")
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=0, sort_bucket=bucket, chunk=p["chunk"], block=p["block"],
+                      push_order=p["push_order"], sort_tile=sort_tile, record_perm=True)
     sim.step(24)
     run = oracle.Run(cfg, load=False)
     before = []
@@ -334,12 +401,12 @@ def test_sort_permutation_production_size(gpu_lib, bucket):
         assert (x < 0).any()  # absorbed slots to drop
         set_oracle_particles(run, s, x, vx, vp2)
         before.append((x, vx, vp2))
-    print_case(f"production-size sort, bucket {bucket}: sort")
+    print_case(f"production-size sort, bucket {bucket}, sort tile {sort_tile}: sort")
     sim.sort_now()
     perms = run.sort()
     for s in range(2):
         pg = sim.perm(0, s)
-        assert len(pg) > 2 * 16384
+        assert len(pg) > 2 * sort_tile
         assert np.array_equal(pg, perms[s]), s
         xg, vxg, vpg = sim.export_particles(0, s)
         x, vx, vp2 = before[s]
