@@ -318,6 +318,19 @@ def _to_steady(sim, nruns, max_steps, block, prune=False):
     return [s["steady_step"] for s in st], seen, total, steps, [s["error_flags"] for s in st]
 
 
+def _plain_launch(cfg: dict, precision: str):
+    """A lone run's own tuned launch (the autotuner's entry for its
+    signature) and its graph block: the plain side of the time-to-steady
+    comparison runs each sheath as it would run alone, not with the
+    batch's launch."""
+    from paper_1511_08225_amd import autotune
+    p = autotune.tune([cfg], precision)
+    g = max(16, p["sort_every"])
+    kw = dict(precision=precision, sort_every=p["sort_every"], sort_bucket=p["sort_bucket"], chunk=p["chunk"],
+              block=p["block"], graph_steps=g, push_order=p.get("push_order", 0), sort_tile=p.get("sort_tile", 0))
+    return kw, g * max(1, 256 // g), p
+
+
 def steady_bench(args) -> int:
     """Wall time to the steady sheath (wall-potential detector) from cold
     loads: all runs batched in one context, each run retired (frozen) by the
@@ -340,11 +353,12 @@ def steady_bench(args) -> int:
         b_steady, b_seen, b_total, b_steps, b_err = _to_steady(sim, len(cfgs), args.max_steps, block, prune=True)
         sim.close()
         for r in range(min(args.plain_runs, len(cfgs))):
-            one = slpic.Sim([cfgs[r]], **kw)  # same run id: the same realisation as in the batch
-            s1, seen1, tot1, steps1, err1 = _to_steady(one, 1, args.max_steps, block)
+            kw1, block1, p1 = _plain_launch(cfgs[r], args.precision)
+            one = slpic.Sim([cfgs[r]], **kw1)  # same run id: the same realisation as in the batch
+            s1, seen1, tot1, steps1, err1 = _to_steady(one, 1, args.max_steps, block1)
             one.close()
             plain.append({"run": r, "steady_step": s1[0], "seconds": seen1[0] if seen1[0] is not None else tot1,
-                          "reached": seen1[0] is not None, "error_flags": err1[0]})
+                          "reached": seen1[0] is not None, "error_flags": err1[0], "launch": p1})
     n_b = sum(1 for s in b_seen if s is not None)
     plain_mean = sum(p["seconds"] for p in plain) / max(len(plain), 1)
     print(json.dumps({
@@ -393,8 +407,9 @@ def time_to_steady(args, runs: int = 256, plain_runs: int = 16, max_steps: int =
         cold_means = [st["window_mean"][0] for st in sim.status()]
         sim.close()
         for r in range(min(plain_runs, len(cfgs))):
-            one = slpic.Sim([cfgs[r]], **kw)
-            s1, seen1, tot1, _, err1 = _to_steady(one, 1, max_steps, block)
+            kw1, block1, _ = _plain_launch(cfgs[r], args.precision)
+            one = slpic.Sim([cfgs[r]], **kw1)
+            s1, seen1, tot1, _, err1 = _to_steady(one, 1, max_steps, block1)
             one.close()
             plain.append({"run": r, "steady_step": s1[0], "seconds": seen1[0] if seen1[0] is not None else tot1,
                           "censored": seen1[0] is None, "error_flags": err1[0]})
@@ -435,6 +450,7 @@ def time_to_steady(args, runs: int = 256, plain_runs: int = 16, max_steps: int =
     return {
         "metric": "time to the steady sheath, batched (cold start) vs plain one at a time", "unit": "s",
         "runs": len(cfgs), "plain_runs_timed": len(plain), "max_steps": max_steps, "launch": params,
+        "plain_launch": "each plain run with its own tuned launch (the autotuner's entry for its signature)",
         "criterion": "device detector: three window means of Phi_w (nx/4 steps each) within 2 % of their average",
         "batched_seconds": b_total, "batched_steady": n_b, "batched_censored": cens_b,
         "plain_seconds_mean_per_run": plain_mean, "plain_censored": cens_p,
