@@ -55,21 +55,34 @@ def _load_cache(path: str) -> dict:
     return {}
 
 
+MIN_TRIAL_SECONDS = 0.025  # a trial's timed steps span at least this (small run sets: more steps)
+MAX_TRIAL_STEPS = 4096
+
+
 def measure(configs: list[dict], precision: str, params: dict, steps: int = 64, warmup: int = 32) -> float:
     """Seconds per particle-step of the whole step (push, source, field,
-    amortised sort) with these parameters, over `steps` graph-replayed steps
-    after `warmup` steps from the cold load; infinite if any run raised an
-    error flag (a sort period too long for its slot headroom overflows)."""
+    amortised sort) with these parameters, over graph-replayed steps after
+    `warmup` steps from the cold load: `steps`, or as many more whole graph
+    blocks (at most MAX_TRIAL_STEPS) as the warm-up's pace says span
+    MIN_TRIAL_SECONDS, so that host timing noise stays small for small run
+    sets; infinite if any run raised an error flag (a sort period too long
+    for its slot headroom overflows)."""
     se = params["sort_every"]
     g = max(16, se)
     steps = max(g, (steps // g) * g)
-    warmup = max(g, (warmup // g) * g)
+    warmup = max(2 * g, (warmup // g) * g)  # the first block captures the graph; the last one is timed
     sim = slpic.Sim(configs, precision=precision, sort_every=se, sort_bucket=params["sort_bucket"],
                     chunk=params["chunk"], block=params["block"], graph_steps=g,
                     push_order=params.get("push_order", 0), sort_tile=params.get("sort_tile", 0))
     try:
-        sim.step(warmup)
+        sim.step(warmup - g)
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(g)  # the last warm-up block, timed for the pace
+        torch.cuda.synchronize()
+        per_step = (time.perf_counter() - t0) / g
+        want = math.ceil(MIN_TRIAL_SECONDS / max(per_step, 1e-9) / g) * g
+        steps = min(max(steps, want), max(steps, MAX_TRIAL_STEPS // g * g))
         p0 = sim.pushed_total()
         t0 = time.perf_counter()
         sim.step(steps)

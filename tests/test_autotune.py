@@ -80,4 +80,7 @@ def test_tune_real_step_small_batch(gpu_lib, tmp_path):
     for k, v in got.items():
         assert v in autotune.CANDIDATES[k]
     rec = json.load(open(path))[autotune.signature(cfgs, "f32")]
-    assert rec["ps_per_push"] == min(t["ps_per_push"] for t in rec["trials"])
+    # the chosen trial is within the switch margin of the fastest one
+    times = [t["ps_per_push"] for t in rec["trials"]]
+    assert rec["ps_per_push"] in times
+    assert rec["ps_per_push"] * (1.0 - autotune.SWITCH_MARGIN) <= min(times) * (1.0 + 1e-12)
