@@ -21,7 +21,7 @@ import torch
 from . import slpic
 
 CANDIDATES = {
-    "chunk": (256, 512, 1024),
+    "chunk": (128, 256, 512, 1024),
     "block": (64, 128, 256),
     "sort_every": (8, 16, 32, 64),
     "sort_bucket": (1, 2, 4),

@@ -196,16 +196,19 @@ def test_smooth_beta_lockstep_f64(gpu_lib):
         _compare_step(sim, run)
 
 
-@pytest.mark.parametrize("u_over_vti", [2.0, 10.0, math.inf])
-def test_one_step_f32_developed_sheath(gpu_lib, u_over_vti):
+@pytest.mark.parametrize("u_over_vti,chunk", [(2.0, 0), (10.0, 0), (math.inf, 0), (2.0, 64), (2.0, 128),
+                                              (2.0, 256), (2.0, 1024)])
+def test_one_step_f32_developed_sheath(gpu_lib, u_over_vti, chunk):
     """FP32 particles: charge per species within 1e-5 after one step from a
-    developed oracle state (256 cells, 200 per cell per species)."""
+    developed oracle state (256 cells, 200 per cell per species), with the
+    default push chunk (512 particles per wavefront) and at u = 2 v_ti with
+    every other chunk the autotuner may pick (1 to 16 particles per lane)."""
     cfg = workloads.sheath(nx=256, ppc=200, u_over_vti=u_over_vti, te_over_ti=20.0, sort_every=1,
                            seed=5)
     run = oracle.Run(cfg)
     run.step(60 if math.isfinite(u_over_vti) else 200)
-    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=1)
-    print_case(f"f32 one step u/vti={u_over_vti}")
+    sim = gpu_lib.Sim(cfg, precision="f32", sort_every=1, chunk=chunk)
+    print_case(f"f32 one step u/vti={u_over_vti} chunk={chunk}")
     push_oracle_to_gpu(sim, 0, run, quantize=True)
     g0, o0 = sim.grid(0), run.grid()
     for s in range(2):
